@@ -1,0 +1,201 @@
+/*
+ * mlmq.h -- C ABI of the MI355X (gfx950) Multi-Level-Multi-Queue SSSP library.
+ *
+ * Problem (Section 2.1): a directed graph G(V, E, W) with non-negative integer
+ * edge weights and a source s; the result is L(s), the shortest path length
+ * from s to every vertex. Here distances are uint32 and MLMQ_UNREACHABLE
+ * (0xFFFFFFFF) marks vertices with no path from s; the largest finite distance
+ * is 2^32 - 2. The result is unique, so every queue configuration, batch and
+ * serving mix returns the same vector.
+ *
+ * Method (Sections 3-4): a persistent GPU kernel relaxes edges while its work
+ * items sit in queues at three levels -- per-lane registers (L0), per-workgroup
+ * LDS (L1: FIFO vector with periodic flush, near-far, or filter), and HBM (L2:
+ * block FIFO or bucket queue) -- moved between levels by unified Read/Write
+ * primitives, with delayed-count global termination detection.
+ *
+ * Conventions for every call:
+ *   - Returns an int status (MLMQ_OK or a negative MLMQ_ERR_*); never throws.
+ *     On failure mlmq_last_error() gives a message for the calling thread.
+ *   - Out-parameters are written only on MLMQ_OK (distance buffers may have
+ *     been partly written on failure).
+ *   - All pointers are plain host or device addresses; sizes are element counts.
+ */
+#ifndef MLMQ_H_
+#define MLMQ_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MLMQ_OK 0
+#define MLMQ_ERR_INVALID_ARG (-1)
+#define MLMQ_ERR_OUT_OF_MEMORY (-2)
+#define MLMQ_ERR_DISTANCE_OVERFLOW (-3)
+#define MLMQ_ERR_QUEUE_CAPACITY (-4)
+#define MLMQ_ERR_TIMEOUT (-5)
+#define MLMQ_ERR_DEVICE (-6)
+#define MLMQ_ERR_CANCELED (-7)
+#define MLMQ_ERR_BUSY (-8)
+
+#define MLMQ_UNREACHABLE 0xFFFFFFFFu
+
+/* mlmq_graph_create flags */
+#define MLMQ_MEM_HOST 0u   /* CSR arrays are host memory; they are copied to the device */
+#define MLMQ_MEM_DEVICE 1u /* CSR arrays are device memory; they are copied on the device */
+
+/* L1 (per-workgroup LDS) queue types, Section 3.4 and Table 1 */
+#define MLMQ_L1_NONE 0    /* no L1: L0 spills straight to L2 */
+#define MLMQ_L1_VEC 1     /* L1V: FIFO vector, flushed to L2 after every l1_flush_wb writes */
+#define MLMQ_L1_NEARFAR 2 /* L1NF: near/far vectors split at NF, NF = min(far) + delta1 */
+#define MLMQ_L1_FILTER 3  /* L1FQ: keeps d <= F, the rest goes to L2; F = min(L2 batch) + delta1 */
+
+/* L2 (HBM) queue types, Section 4.2 and Table 1 */
+#define MLMQ_L2_FIFO 0   /* L2V: block-based lock-free FIFO ring */
+#define MLMQ_L2_BUCKET 1 /* L2DQ: bmax FIFO rings as buckets of width delta2 */
+
+/* Counters a solve reports (summed over all waves). */
+typedef struct mlmq_stats {
+  uint32_t struct_size;
+  uint32_t status;         /* device status word of the last solve */
+  double kernel_ms;        /* device time of init + persistent kernel (HIP events) */
+  uint64_t expansions;     /* work items that passed the stale check */
+  uint64_t stale;          /* work items dropped as stale */
+  uint64_t edges;          /* edges scanned */
+  uint64_t pushes;         /* successful relaxations (improved distances) */
+  uint64_t l1_writes;      /* L1 Write calls */
+  uint64_t l1_reads;       /* L1 Read calls that returned work */
+  uint64_t l2_writes;      /* L2 blocks written */
+  uint64_t l2_reads;       /* L2 blocks read */
+  uint64_t hub_chunks;     /* grid-cooperative edge chunks processed */
+  uint64_t flushes;        /* L1V periodic flushes */
+  uint32_t grid_wgs;       /* workgroups launched */
+  uint32_t retries;        /* capacity retries taken */
+} mlmq_stats;
+
+/*
+ * Queue configuration (the search space of Section 3.5; every knob has a
+ * default). Zero-initialise, set struct_size = sizeof(mlmq_config), call
+ * mlmq_config_default, then change fields. Read only during a call.
+ */
+typedef struct mlmq_config {
+  uint32_t struct_size;
+  uint8_t l0_rows;   /* L0 capacity in 64-element rows per wave, 0..4 (0 = L0 off) */
+  uint8_t l1_type;   /* MLMQ_L1_* */
+  uint8_t l2_type;   /* MLMQ_L2_* */
+  uint8_t reserved0;
+  uint32_t l1_cap;      /* L1 capacity per workgroup in elements (power of two, 64..8192) */
+  uint32_t l1_flush_wb; /* L1V: flush all of L1 to L2 after every wb L1 writes (0 = never) */
+  uint32_t delta1;      /* L1NF / L1FQ threshold step (distance units, >= 1) */
+  uint32_t delta2_log2; /* L2 bucket width = 2^delta2_log2 */
+  uint32_t bmax;        /* L2 bucket count (1..64) */
+  uint32_t bnum;        /* buckets scanned per L2 read (1..bmax) */
+  uint32_t th_v;        /* degree above which a whole wave expands one vertex */
+  uint32_t th_hub;      /* degree above which edges are split into grid-wide chunks (0 = off) */
+  uint32_t hub_chunk;   /* edges per grid-wide chunk (multiple of 64) */
+  uint32_t wg_size;     /* threads per workgroup: 64 (one wave; L1 is private to it) */
+  uint32_t grid_wgs;    /* persistent workgroups (0 = as many as fit on the device) */
+  uint64_t l2_capacity; /* L2 elements per query (0 = automatic); grows on overflow */
+  void* stream;         /* hipStream_t to run on (NULL = null stream) */
+  uint32_t timeout_ms;  /* device-side watchdog per solve (0 = 60000) */
+  uint32_t max_retries; /* capacity-overflow retries with a doubled L2 (default 3) */
+  mlmq_stats* stats_out; /* nullable: receives counters of the solve */
+} mlmq_config;
+
+typedef struct mlmq_graph mlmq_graph;   /* opaque; immutable after create */
+typedef struct mlmq_server mlmq_server; /* opaque */
+
+/* Graph features of Table 2 (Section 3.5), computed in one O(n+m) pass. */
+typedef struct mlmq_features {
+  double n, nnz, avg_deg, max_deg, std_deg, avg_w, std_w, max_w;
+} mlmq_features;
+
+/* Fills cfg with defaults (cfg->struct_size must be set). */
+int mlmq_config_default(mlmq_config* cfg);
+
+/*
+ * Builds a device-resident graph from CSR (Section 2.1; the graph stays in HBM
+ * across solves). n >= 1 vertices, m >= 0 directed edges, m < 2^31.
+ * row_offsets[n+1] (row_offsets[0] = 0, non-decreasing, row_offsets[n] = m),
+ * col[m] in [0, n), w[m] any uint32 (0, self-loops and parallel edges allowed).
+ * flags: MLMQ_MEM_HOST or MLMQ_MEM_DEVICE tells where the arrays live; they
+ * are copied, so the caller keeps ownership. Validation is O(n+m); errors give
+ * MLMQ_ERR_INVALID_ARG. Needs a HIP device (else MLMQ_ERR_DEVICE).
+ */
+int mlmq_graph_create(int32_t n, int64_t m, const int32_t* row_offsets, const int32_t* col,
+                      const uint32_t* w, uint32_t flags, mlmq_graph** out);
+void mlmq_graph_destroy(mlmq_graph* g);
+int mlmq_graph_info(const mlmq_graph* g, int32_t* n, int64_t* m, mlmq_features* f);
+
+/*
+ * The config a solve on g uses when cfg == NULL: the autotuned one if
+ * mlmq_autotune ran, else defaults adjusted by the Table 2 features.
+ * out->struct_size must be set; stream and stats_out are left NULL.
+ */
+int mlmq_graph_config(const mlmq_graph* g, mlmq_config* out);
+
+/*
+ * Table 2 features of a host CSR, without a device. Same validation as
+ * mlmq_graph_create.
+ */
+int mlmq_features_host(int32_t n, int64_t m, const int32_t* row_offsets, const int32_t* col,
+                       const uint32_t* w, mlmq_features* out);
+
+/*
+ * Single-source solve (Section 2.1 / Section 4.1). dist_out: n uint32, host or
+ * device memory, caller-owned; receives L(s). cfg NULL = the autotuned config
+ * cached for this graph if any, else defaults. Enqueues on cfg->stream and
+ * returns after the solve finished. source >= n gives MLMQ_ERR_INVALID_ARG.
+ * MLMQ_ERR_DISTANCE_OVERFLOW if a reachable vertex's distance is >= 2^32 - 1.
+ * MLMQ_ERR_TIMEOUT if the device watchdog fired.
+ */
+int mlmq_sssp(const mlmq_graph* g, uint32_t source, uint32_t* dist_out, const mlmq_config* cfg);
+
+/*
+ * Many queries in one persistent launch. Query i solves graphs[i] from
+ * sources[i] into dist_outs[i] (device memory, n_i uint32 each). cfgs may be
+ * NULL (per-graph autotuned/default) or hold one config per query; launch
+ * shape and stream come from cfgs[0] (or defaults). per_query_status may be
+ * NULL or receive each query's status. Output per query is identical to
+ * mlmq_sssp alone. Returns the first non-OK query status, else MLMQ_OK.
+ */
+int mlmq_sssp_batch(const mlmq_graph* const* graphs, const uint32_t* sources, uint32_t* const* dist_outs,
+                    int32_t nq, const mlmq_config* const* cfgs, int32_t* per_query_status);
+
+/*
+ * Empirical autotuner (Section 3.5's input-adaptive configuration, as a timed
+ * search): candidates pruned by the Table 2 features, each timed on seeded
+ * sources; the best is cached for the graph (used by cfg == NULL) and written
+ * to *out. budget_ms bounds the search time (0 = default 2000).
+ */
+int mlmq_autotune(mlmq_graph* g, uint32_t budget_ms, mlmq_config* out);
+
+/*
+ * Continuous-batching server over resident graphs: a resident persistent
+ * kernel picks up queries from a slot table while others run. Queries are
+ * admitted in arrival order when a slot and mem_budget_bytes of per-query
+ * state (distances + queues) are free. submit never blocks (MLMQ_ERR_BUSY if
+ * the pending list is full); dist_out is device memory of graphs[graph_id]'s n.
+ */
+int mlmq_server_create(const mlmq_graph* const* graphs, int32_t ngraphs, uint64_t mem_budget_bytes,
+                       int32_t max_slots, const mlmq_config* cfg, mlmq_server** out);
+int mlmq_server_submit(mlmq_server* s, int32_t graph_id, uint32_t source, uint32_t* dist_out,
+                       uint64_t* ticket);
+/* Non-blocking; *done_status = 1 (not finished) or the query's final status. */
+int mlmq_server_poll(mlmq_server* s, uint64_t ticket, int32_t* done_status);
+/* Blocks up to timeout_ms; returns the query's status or MLMQ_ERR_TIMEOUT. */
+int mlmq_server_wait(mlmq_server* s, uint64_t ticket, uint32_t timeout_ms);
+/* Timestamps (ns, host monotonic clock) of submission and completion. */
+int mlmq_server_times(mlmq_server* s, uint64_t ticket, uint64_t* submit_ns, uint64_t* done_ns);
+void mlmq_server_destroy(mlmq_server* s);
+
+/* Message for the calling thread's last non-OK return. */
+const char* mlmq_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MLMQ_H_ */

@@ -1,0 +1,325 @@
+// Batched solves in one persistent, hipGraph-captured launch, and the
+// empirical autotuner.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/mlmq.h"
+#include "mlmq_api_internal.h"
+#include "mlmq_internal.h"
+
+using namespace mlmq;
+
+namespace {
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+uint64_t mix(uint64_t h, uint64_t x) {
+  h ^= x + 0x9E3779B97F4A7C15ull + (h << 6) + (h >> 2);
+  return h;
+}
+
+hipStream_t internal_stream() {
+  static hipStream_t s = nullptr;
+  static std::once_flag once;
+  std::call_once(once, [] { (void)hipStreamCreateWithFlags(&s, hipStreamNonBlocking); });
+  return s;
+}
+
+bool device_ptr(const void* p) {
+  hipPointerAttribute_t at;
+  if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return at.type == hipMemoryTypeDevice || at.type == hipMemoryTypeManaged;
+}
+
+}  // namespace
+
+extern "C" int mlmq_sssp_batch(const mlmq_graph* const* graphs, const uint32_t* sources, uint32_t* const* dist_outs,
+                               int32_t nq, const mlmq_config* const* cfgs, int32_t* per_query_status) {
+  if (nq < 1 || !graphs || !sources || !dist_outs) return set_error(MLMQ_ERR_INVALID_ARG, "empty or NULL batch");
+  int rc = need_device();
+  if (rc) return rc;
+  std::vector<mlmq_config> conf((size_t)nq);
+  for (int32_t i = 0; i < nq; ++i) {
+    if (!graphs[i]) return set_error(MLMQ_ERR_INVALID_ARG, "graphs[%d] is NULL", i);
+    if (sources[i] >= (uint32_t)graphs[i]->n)
+      return set_error(MLMQ_ERR_INVALID_ARG, "sources[%d] = %u out of range", i, sources[i]);
+    if (!dist_outs[i] || !device_ptr(dist_outs[i]))
+      return set_error(MLMQ_ERR_INVALID_ARG, "dist_outs[%d] must be device memory", i);
+    mlmq_config tmp;
+    conf[i] = *resolve_config(graphs[i], cfgs ? cfgs[i] : nullptr, &tmp);
+    rc = check_config(&conf[i]);
+    if (rc) return rc;
+  }
+  // Launch shape from the first config; LDS sized for the largest L1.
+  mlmq_config lc = conf[0];
+  uint32_t l1cap = 64;
+  bool two = false;
+  for (auto& c : conf) {
+    if (c.l1_type != MLMQ_L1_NONE) l1cap = std::max(l1cap, c.l1_cap);
+    two = two || c.l1_type == MLMQ_L1_NEARFAR;
+  }
+  LaunchShape shape;
+  rc = launch_shape(lc, l1cap, two, &shape);
+  if (rc) return rc;
+  hipStream_t stream = lc.stream ? reinterpret_cast<hipStream_t>(lc.stream) : internal_stream();
+  // Largest queries first, so the long ones start early (LPT order).
+  std::vector<int32_t> order((size_t)nq);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return graphs[a]->m > graphs[b]->m; });
+  const uint32_t conc = (uint32_t)std::min<int32_t>(nq, 16);
+  std::vector<QueryPlan> plans((size_t)nq);
+  size_t bytes = 0;
+  uint32_t init_words = 1;
+  for (int32_t k = 0; k < nq; ++k) {
+    const int32_t i = order[k];
+    plans[k] = plan_query(graphs[i], conf[i], 0, 1);
+    bytes = align_up(bytes + plans[k].bytes, 256);
+    init_words = std::max(init_words, plans[k].init_words);
+  }
+  const size_t desc_off = bytes;
+  const size_t batch_off = align_up(desc_off + sizeof(QueryDesc) * nq, 256);
+  const size_t res_off = align_up(batch_off + sizeof(BatchCtrl), 256);
+  const size_t beats_off = align_up(res_off + sizeof(QueryResult) * nq, 256);
+  const size_t dev_bytes = align_up(beats_off + 4ull * shape.grid, 256);
+  const size_t host_bytes = sizeof(QueryDesc) * nq + sizeof(QueryResult) * nq + 64;
+  Slab* slab = nullptr;
+  rc = slab_acquire(dev_bytes, host_bytes, &slab);
+  if (rc) return rc;
+  char* base = static_cast<char*>(slab->dev);
+  QueryDesc* d_desc = reinterpret_cast<QueryDesc*>(base + desc_off);
+  BatchCtrl* d_batch = reinterpret_cast<BatchCtrl*>(base + batch_off);
+  QueryResult* d_res = reinterpret_cast<QueryResult*>(base + res_off);
+  QueryDesc* h_desc = reinterpret_cast<QueryDesc*>(slab->host);
+  QueryResult* h_res = reinterpret_cast<QueryResult*>(h_desc + nq);
+  size_t off = 0;
+  for (int32_t k = 0; k < nq; ++k) {
+    const int32_t i = order[k];
+    const mlmq_config& c = conf[i];
+    const uint32_t want = c.grid_wgs ? std::min(c.grid_wgs, shape.grid) : std::max<uint32_t>(4, shape.grid / conc);
+    h_desc[k] = make_desc(graphs[i], c, plans[k], base + off, dist_outs[i], sources[i], want);
+    off = align_up(off + plans[k].bytes, 256);
+  }
+  uint32_t* d_beats = reinterpret_cast<uint32_t*>(base + beats_off);
+  const LaunchArgs a = make_args(d_desc, d_batch, nq, shape, lc.timeout_ms, d_beats);
+  uint64_t key = 0x6d6c6d71ull;
+  for (uint64_t x : {(uint64_t)nq, (uint64_t)shape.grid, (uint64_t)shape.wg, (uint64_t)shape.lds,
+                     (uint64_t)init_words, (uint64_t)(uintptr_t)stream, a.timeout_ticks, (uint64_t)shape.l1_cap,
+                     (uint64_t)shape.two})
+    key = mix(key, x);
+  hipError_t e = hipMemcpyAsync(d_desc, h_desc, sizeof(QueryDesc) * nq, hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess && (!slab->graph_exec || slab->graph_key != key)) {
+    if (slab->graph_exec) {
+      (void)hipGraphExecDestroy(slab->graph_exec);
+      slab->graph_exec = nullptr;
+    }
+    // Capture init + persistent worker + result gather as one graph.
+    hipGraph_t graph = nullptr;
+    e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      hipError_t e1 = launch_init(d_desc, d_batch, nq, init_words, stream);
+      if (e1 == hipSuccess) e1 = launch_worker(a, shape.grid, shape.wg, shape.lds, stream);
+      if (e1 == hipSuccess) e1 = launch_gather(d_desc, nq, d_res, stream);
+      e = hipStreamEndCapture(stream, &graph);
+      if (e == hipSuccess) e = e1;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&slab->graph_exec, graph, nullptr, nullptr, 0);
+    if (graph) hipGraphDestroy(graph);
+    if (e == hipSuccess) slab->graph_key = key;
+  }
+  if (e == hipSuccess) e = hipGraphLaunch(slab->graph_exec, stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(h_res, d_res, sizeof(QueryResult) * nq, hipMemcpyDeviceToHost, stream);
+  uint32_t* h_one = reinterpret_cast<uint32_t*>(h_res + nq);
+  WatchdogView view;
+  view.d_ctrl = h_desc[0].ctrl;
+  view.d_rings = h_desc[0].rings;
+  view.d_beats = d_beats;
+  view.nbeats = shape.grid;
+  if (e == hipSuccess) e = wait_with_watchdog(stream, lc.timeout_ms, &d_batch->cancel.v, h_one, view);
+  if (e == hipErrorLaunchTimeOut) {
+    const std::string snap = g_last_error;
+    if (hipStreamQuery(stream) == hipSuccess) slab_release(slab);
+    return set_error(MLMQ_ERR_TIMEOUT, "device overran its timeout (%s)", snap.c_str());
+  }
+  if (e != hipSuccess) {
+    slab_release(slab);
+    return hip_fail(e, "batch launch");
+  }
+  int first_bad = MLMQ_OK;
+  std::vector<int32_t> status((size_t)nq, MLMQ_OK);
+  std::vector<int32_t> redo;
+  for (int32_t k = 0; k < nq; ++k) {
+    const int32_t i = order[k];
+    int st = status_to_code(h_res[k].error);
+    if (st == MLMQ_ERR_QUEUE_CAPACITY) {
+      redo.push_back(i);  // solved again alone, with its own capacity retries
+      continue;
+    }
+    if (st == MLMQ_OK && h_res[k].overflow && !graphs[i]->overflow_safe) redo.push_back(i);
+    status[i] = st;
+    if (cfgs && cfgs[i] && cfgs[i]->stats_out) {
+      QueryCtrl tmp;
+      std::memset(&tmp, 0, sizeof(tmp));
+      tmp.error.v = h_res[k].error;
+      for (int j = 0; j < kNumCounters; ++j) tmp.stats[j] = h_res[k].stats[j];
+      fill_stats(cfgs[i]->stats_out, tmp, 0.0, h_desc[k].want_wgs, 0);
+    }
+  }
+  slab_release(slab);
+  for (int32_t i : redo) {
+    mlmq_config c = conf[i];
+    c.stream = reinterpret_cast<void*>(stream);
+    status[i] = run_single(graphs[i], sources[i], dist_outs[i], c);
+  }
+  for (int32_t i = 0; i < nq; ++i) {
+    if (per_query_status) per_query_status[i] = status[i];
+    if (status[i] != MLMQ_OK && first_bad == MLMQ_OK) first_bad = status[i];
+  }
+  if (first_bad != MLMQ_OK) set_error(first_bad, "at least one query of the batch failed");
+  return first_bad;
+}
+
+// ------------------------------------------------------------ autotuner
+
+namespace {
+
+// Candidate configurations, pruned by the Table 2 features with the
+// insights of Section 3.5: power-law graphs are sensitive to priority
+// inversion (priority-aware L1/L2 first); meshes and roads are not, and
+// smaller graphs favour parallel FIFO queues.
+std::vector<mlmq_config> candidates(const mlmq_graph* g) {
+  mlmq_config base;
+  base.struct_size = sizeof(mlmq_config);
+  default_config(&base);
+  heuristic_config(g, &base);
+  const mlmq_features& f = g->features;
+  const bool skewed = f.max_deg > 64 && f.std_deg > f.avg_deg;
+  const uint32_t mw = (uint32_t)std::max(1.0, f.avg_w);
+  std::vector<mlmq_config> out;
+  auto add = [&](uint8_t l0, uint8_t l1, uint8_t l2, uint32_t d1, uint32_t d2l, uint32_t wb, uint32_t wg,
+                 uint32_t grid_div) {
+    mlmq_config c = base;
+    c.l0_rows = l0;
+    c.l1_type = l1;
+    c.l2_type = l2;
+    c.delta1 = d1;
+    c.delta2_log2 = d2l;
+    c.l1_flush_wb = wb;
+    c.wg_size = wg;
+    c.grid_wgs = 0;
+    if (grid_div > 1) {
+      LaunchShape s;
+      if (launch_shape(c, l1 == MLMQ_L1_NONE ? 64u : c.l1_cap, l1 == MLMQ_L1_NEARFAR, &s) == MLMQ_OK)
+        c.grid_wgs = std::max<uint32_t>(1, s.max_grid / grid_div);
+    }
+    out.push_back(c);
+  };
+  uint32_t l2mw = 0;
+  while ((2u << l2mw) <= mw) ++l2mw;
+  add(base.l0_rows, base.l1_type, base.l2_type, base.delta1, base.delta2_log2, base.l1_flush_wb, 64, 1);
+  for (uint8_t l0 : {0, 1, 2, 4}) add(l0, MLMQ_L1_VEC, MLMQ_L2_FIFO, 2 * mw, l2mw, 64, 64, 1);
+  add(2, MLMQ_L1_NONE, MLMQ_L2_FIFO, 2 * mw, l2mw, 0, 64, 1);
+  for (uint32_t d1 : {mw, 4 * mw}) {
+    add(1, MLMQ_L1_NEARFAR, MLMQ_L2_FIFO, d1, l2mw, 0, 64, 1);
+    add(1, MLMQ_L1_FILTER, MLMQ_L2_FIFO, d1, l2mw, 0, 64, 1);
+  }
+  for (uint32_t d2 : {l2mw, l2mw + 2}) {
+    add(1, MLMQ_L1_VEC, MLMQ_L2_BUCKET, 2 * mw, d2, 64, 64, 1);
+    add(1, MLMQ_L1_NEARFAR, MLMQ_L2_BUCKET, 2 * mw, d2, 0, 64, 1);
+  }
+  for (uint32_t div : {2u, 4u, 8u}) add(base.l0_rows, base.l1_type, base.l2_type, base.delta1, base.delta2_log2,
+                                        base.l1_flush_wb, 64, div);
+  if (skewed) {
+    for (auto& c : out) c.th_hub = 8192;
+  } else {
+    for (auto& c : out) c.th_hub = 0;
+  }
+  return out;
+}
+
+}  // namespace
+
+extern "C" int mlmq_autotune(mlmq_graph* g, uint32_t budget_ms, mlmq_config* out) {
+  if (!g) return set_error(MLMQ_ERR_INVALID_ARG, "graph is NULL");
+  int rc = need_device();
+  if (rc) return rc;
+  if (!budget_ms) budget_ms = 2000;
+  uint32_t* d_dist = nullptr;
+  hipError_t e = hipMalloc(&d_dist, 4ull * g->n);
+  if (e != hipSuccess) return hip_fail(e, "autotune buffer");
+  // Seeded sources: the highest-degree vertex plus two spread by a fixed LCG
+  // among vertices with out-degree >= 1 (located on the host copy of offsets).
+  std::vector<int32_t> off((size_t)g->n + 1);
+  e = hipMemcpy(off.data(), g->d_off, 4ull * (g->n + 1), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) {
+    (void)hipFree(d_dist);
+    return hip_fail(e, "autotune offsets");
+  }
+  std::vector<uint32_t> srcs;
+  int32_t best_v = 0, best_d = -1;
+  for (int32_t u = 0; u < g->n; ++u)
+    if (off[u + 1] - off[u] > best_d) {
+      best_d = off[u + 1] - off[u];
+      best_v = u;
+    }
+  srcs.push_back((uint32_t)best_v);
+  uint64_t x = 0x2545F4914F6CDD1Dull;
+  for (int tries = 0; srcs.size() < 3 && tries < 1000; ++tries) {
+    x = x * 6364136223846793005ull + 1442695040888963407ull;
+    const uint32_t u = (uint32_t)((x >> 33) % (uint64_t)g->n);
+    if (off[u + 1] > off[u]) srcs.push_back(u);
+  }
+  const auto t0 = std::chrono::steady_clock::now();
+  std::vector<mlmq_config> cand = candidates(g);
+  double best_ms = 1e300;
+  mlmq_config best = cand[0];
+  for (size_t ci = 0; ci < cand.size(); ++ci) {
+    const double el =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (ci > 0 && el > budget_ms) break;
+    mlmq_config c = cand[ci];
+    mlmq_stats st;
+    std::memset(&st, 0, sizeof(st));
+    st.struct_size = sizeof(st);
+    c.stats_out = &st;
+    c.stream = out ? out->stream : nullptr;
+    double total = 0;
+    bool okc = true;
+    for (uint32_t s : srcs) {
+      if (run_single(g, s, d_dist, c) != MLMQ_OK) {
+        okc = false;
+        break;
+      }
+      total += st.kernel_ms;
+    }
+    if (okc && total < best_ms) {
+      best_ms = total;
+      best = cand[ci];
+    }
+  }
+  (void)hipFree(d_dist);
+  best.stats_out = nullptr;
+  best.stream = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g->mu);
+    g->tuned = best;
+    g->has_tuned = true;
+  }
+  if (out) {
+    mlmq_stats* so = out->stats_out;
+    void* ss = out->stream;
+    *out = best;
+    out->stats_out = so;
+    out->stream = ss;
+  }
+  return MLMQ_OK;
+}

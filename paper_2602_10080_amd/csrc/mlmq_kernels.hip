@@ -1,0 +1,884 @@
+// Multi-Level-Multi-Queue SSSP kernels for CDNA4 (gfx950).
+//
+// One persistent kernel relaxes edges while work items (vertex, distance)
+// live in three levels of queues (Section 3.1):
+//   L0  per wave, in VGPRs: a ring of up to 4 rows x 64 lanes, FIFO;
+//   L1  per workgroup, in LDS: FIFO vector with periodic flush, near-far pair
+//       or filter (Section 3.4). A workgroup is one wave64, so L1 is private
+//       to its wave like the paper's per-warp L1 and needs no lock;
+//   L2  per query, in HBM: block-based FIFO ring(s) with ticket counters
+//       (Section 4.2), one ring for L2V or bmax rings used as Delta buckets
+//       for L2DQ.
+// The worker only talks to the unified Read/Write cascade (Section 3.2-3.3):
+// Read takes from L0, else L1, else the global levels; Write appends to L0,
+// whose overflow moves everything to L1, whose overflow goes to L2.
+// Termination uses delayed counting (Section 4.1): every L2 block (and every
+// grid-wide hub chunk) is reserved when it is written; a wave adds what it
+// took from the global levels to the done count only when it holds nothing
+// (L0 and L1 empty, the global read came back empty); the query is finished
+// when done equals the number reserved.
+//
+// Memory ordering across the 8 XCDs: queue payloads and headers are written
+// and read with agent-scope relaxed atomics, which gfx950 issues with the sc1
+// bit, and publication is ordered by waiting for the payload stores
+// (s_waitcnt vmcnt(0)) before the header store. Distances only ever decrease,
+// so plain (possibly stale) loads of dist[] are safe filters; the
+// authoritative update is the atomicMin.
+//
+// Every wait is bounded by the device watchdog deadline and the host's cancel
+// flag, and every cross-lane operation runs with the whole wave active.
+
+#include "mlmq_internal.h"
+
+#include "../../include/mlmq.h"
+
+namespace mlmq {
+namespace {
+
+// ------------------------------------------------------------ wave helpers
+
+__device__ __forceinline__ uint32_t lane() { return __lane_id(); }
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+__device__ __forceinline__ uint32_t popc(uint64_t m) { return (uint32_t)__popcll(m); }
+__device__ __forceinline__ uint32_t first_lane(uint64_t m) { return (uint32_t)__ffsll((long long)m) - 1; }
+__device__ __forceinline__ uint32_t rank_of(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+__device__ __forceinline__ uint32_t uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ uint32_t lane_val(uint32_t x, uint32_t l) { return __builtin_amdgcn_readlane(x, l); }
+__device__ __forceinline__ uint64_t uni64(uint64_t x) {
+  return ((uint64_t)uni((uint32_t)(x >> 32)) << 32) | uni((uint32_t)x);
+}
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t x) {
+#pragma unroll
+  for (int o = 32; o; o >>= 1) x += __shfl_xor(x, o);
+  return x;
+}
+__device__ __forceinline__ uint32_t wave_min(uint32_t x) {
+#pragma unroll
+  for (int o = 32; o; o >>= 1) x = min(x, (uint32_t)__shfl_xor(x, o));
+  return x;
+}
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    uint32_t y = __shfl_up(x, o);
+    if (lane() >= (uint32_t)o) x += y;
+  }
+  return x;
+}
+
+// Coherent (agent-scope) accesses: sc1 loads/stores, device-wide atomics.
+__device__ __forceinline__ uint32_t ld32(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t ld64(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st32(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st64(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t add32(uint32_t* p, uint32_t v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ bool cas32(uint32_t* p, uint32_t expect, uint32_t v) {
+  return __hip_atomic_compare_exchange_strong(p, &expect, v, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+}
+// Plain cached load of a distance label (may be stale, i.e. too large).
+__device__ __forceinline__ uint32_t ld_label(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+// Wait until every vector memory operation of this wave has completed.
+__device__ __forceinline__ void vm_drain() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+__device__ __forceinline__ void compiler_fence() { asm volatile("" ::: "memory"); }
+
+__device__ __forceinline__ uint32_t elem_v(uint64_t e) { return (uint32_t)e; }
+__device__ __forceinline__ uint32_t elem_d(uint64_t e) { return (uint32_t)(e >> 32); }
+__device__ __forceinline__ uint64_t make_elem(uint32_t v, uint32_t d) { return (uint64_t)v | ((uint64_t)d << 32); }
+__device__ __forceinline__ uint32_t sat_add(uint32_t a, uint32_t b) { return a > kInf - b ? kInf : a + b; }
+
+// Sleep for roughly 64 * 2^level cycles (level 0..6); level is wave-uniform,
+// so exactly one s_sleep runs.
+__device__ __forceinline__ void backoff(uint32_t level) {
+  switch (uni(level)) {
+    case 0: __builtin_amdgcn_s_sleep(1); break;
+    case 1: __builtin_amdgcn_s_sleep(2); break;
+    case 2: __builtin_amdgcn_s_sleep(4); break;
+    case 3: __builtin_amdgcn_s_sleep(8); break;
+    case 4: __builtin_amdgcn_s_sleep(16); break;
+    case 5: __builtin_amdgcn_s_sleep(32); break;
+    default: __builtin_amdgcn_s_sleep(64); break;
+  }
+}
+
+// ------------------------------------------------------------ wave state
+
+struct Ctx {
+  QueryDesc q;
+  uint64_t* stg;  // 64-entry staging row (LDS)
+  uint64_t* l1;   // L1 main (or near) ring (LDS)
+  uint64_t* far;  // L1 far ring (LDS, near-far only)
+  uint32_t l1mask;
+  uint32_t qh, qt, fh, ft;   // L1 ring counters (monotonic)
+  uint32_t thresh;           // NF (near-far) or F (filter)
+  uint32_t wcount;           // L1 writes since the last periodic flush
+  uint32_t done_acc;         // blocks / hub chunks taken, not yet added to done
+  uint32_t pend;             // lane r: claimed but unpublished ticket of ring r
+  const uint32_t* cancel;    // host-set flag: stop now
+  uint64_t deadline;         // device watchdog (wall-clock ticks)
+  uint64_t cap_wait;         // longest wait for a free L2 slot
+  uint64_t r0, r1, r2, r3;   // L0 rows (per lane)
+  uint32_t l0h, l0n;         // L0 head position and count
+  uint32_t* beat;            // this wave's heartbeat word (nullable)
+  uint32_t it;               // loop iterations (heartbeat)
+  bool stop;                 // leave the query (terminated or failed)
+  bool ovf;                  // a candidate distance overflowed
+  uint32_t ct[kNumCounters]; // per-wave counters
+};
+
+__device__ __forceinline__ void fail(Ctx& c, uint32_t code) {
+  if (lane() == 0) {
+    cas32(&c.q.ctrl->error.v, kStOk, code);
+    st32(&c.q.ctrl->terminate.v, 1u);
+  }
+  c.stop = true;
+}
+
+// Heartbeat: written through to memory so the host can read it while the
+// kernel runs (a diagnostic for the host watchdog).
+__device__ __forceinline__ void beat(uint32_t* b, uint32_t point, uint32_t it) {
+  if (b && lane() == 0)
+    __hip_atomic_store(b, (point << 24) | (it & 0xFFFFFFu), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+__device__ __forceinline__ bool past_deadline(const Ctx& c) { return (uint64_t)wall_clock64() > c.deadline; }
+__device__ __forceinline__ bool canceled(const Ctx& c) { return uni(ld32(c.cancel)) != 0; }
+
+// Watchdog and cancel test; true if the wave must leave the query.
+__device__ __forceinline__ bool must_stop(Ctx& c) {
+  if (uni(ld32(&c.q.ctrl->terminate.v))) return true;
+  if (past_deadline(c)) {
+    fail(c, kStTimeout);
+    return true;
+  }
+  if (canceled(c)) {
+    fail(c, kStCanceled);
+    return true;
+  }
+  return false;
+}
+
+// ------------------------------------------------------------ L0 (VGPR ring)
+
+// Rows are picked with masks rather than an index, so no row is ever
+// addressed through memory and all four stay in VGPRs.
+__device__ __forceinline__ uint64_t row_mask(uint32_t row, uint32_t i) { return 0ull - (uint64_t)(row == i); }
+__device__ __forceinline__ uint64_t l0_get(const Ctx& c, uint32_t row) {
+  return (c.r0 & row_mask(row, 0)) | (c.r1 & row_mask(row, 1)) | (c.r2 & row_mask(row, 2)) |
+         (c.r3 & row_mask(row, 3));
+}
+__device__ __forceinline__ void l0_set(Ctx& c, uint32_t row, uint64_t x, bool p) {
+  const uint64_t keep = p ? 0ull : ~0ull;
+  const uint64_t m0 = row_mask(row, 0) & ~keep, m1 = row_mask(row, 1) & ~keep;
+  const uint64_t m2 = row_mask(row, 2) & ~keep, m3 = row_mask(row, 3) & ~keep;
+  c.r0 = (c.r0 & ~m0) | (x & m0);
+  c.r1 = (c.r1 & ~m1) | (x & m1);
+  c.r2 = (c.r2 & ~m2) | (x & m2);
+  c.r3 = (c.r3 & ~m3) | (x & m3);
+}
+// L0 Read: up to 64 elements from the head; lane j gets the one element of the
+// window whose ring position is congruent to j (mod 64), so no lane movement.
+__device__ __forceinline__ void l0_read(Ctx& c, uint64_t& e, bool& ok) {
+  const uint32_t cap = c.q.l0_cap;
+  const uint32_t k = min(c.l0n, 64u);
+  const uint32_t off = (lane() - c.l0h) & 63u;
+  ok = off < k;
+  uint32_t pos = c.l0h + off;
+  if (pos >= cap) pos -= cap;
+  e = l0_get(c, pos >> 6);
+  c.l0h += k;
+  if (c.l0h >= cap) c.l0h -= cap;
+  c.l0n -= k;
+}
+// Compact the lanes with ok into the staging row, in lane order.
+__device__ __forceinline__ void stage(Ctx& c, uint64_t e, bool ok) {
+  const uint64_t m = ballot(ok);
+  if (ok) c.stg[rank_of(m)] = e;
+  compiler_fence();
+}
+// L0 Write: append the k staged elements at the tail (caller ensures room).
+__device__ __forceinline__ void l0_append(Ctx& c, uint32_t k) {
+  const uint32_t cap = c.q.l0_cap;
+  uint32_t base = c.l0h + c.l0n;
+  if (base >= cap) base -= cap;
+  const uint32_t off = (lane() - base) & 63u;
+  const bool p = off < k;
+  const uint64_t x = p ? c.stg[off] : 0;
+  uint32_t pos = base + off;
+  if (pos >= cap) pos -= cap;
+  l0_set(c, pos >> 6, x, p);
+  c.l0n += k;
+  compiler_fence();
+}
+
+// ------------------------------------------------------------ L2 (HBM rings)
+
+// Write one block of up to 64 elements to ring `ring` (Section 4.2, L2 FIFO:
+// one atomicAdd per block). The ticket counter doubles as the termination
+// reservation. Slot states: 2*lap = free for lap, 2*lap+1 = full for lap.
+__device__ __forceinline__ bool l2_put_block(Ctx& c, uint32_t ring, uint64_t e, bool ok, uint64_t m) {
+  const uint32_t k = popc(m);
+  uint32_t t = 0;
+  if (lane() == 0) t = add32(&c.q.rings[ring].tail.v, 1u);
+  t = lane_val(t, 0);
+  const uint32_t nb = c.q.nb_log2;
+  const uint32_t slot = t & ((1u << nb) - 1u);
+  const uint32_t lap = t >> nb;
+  const uint64_t bidx = ((uint64_t)ring << nb) + slot;
+  uint64_t* h = c.q.hdr + bidx;
+  // The slot is reusable once the previous lap's reader released it; a ring
+  // that stays full for longer than the capacity wait is an overflow.
+  uint64_t t_wait = 0;
+  for (uint32_t spins = 0;; ++spins) {
+    const uint32_t seq = uni((uint32_t)(ld64(h) >> 32));
+    if (seq == 2u * lap) break;
+    if ((spins & 63u) == 0) {
+      beat(c.beat, kPtL2Wait, spins);
+      const uint64_t now = (uint64_t)wall_clock64();
+      if (spins == 0) t_wait = now;
+      if (now - t_wait > c.cap_wait || now > c.deadline) {
+        fail(c, kStCapacity);
+        return false;
+      }
+    }
+    __builtin_amdgcn_s_sleep(2);
+  }
+  uint64_t* dst = c.q.data + (bidx << 6);
+  if (ok) st64(dst + rank_of(m), e);
+  vm_drain();
+  if (lane() == 0) st64(h, ((uint64_t)(2u * lap + 1u) << 32) | k);
+  c.ct[kCtL2Writes] += 1;
+  return true;
+}
+
+// L2 Write of a lane vector. Bucket queue (Section 4.2, L2DQ): bucket index
+// floor(d / Delta) relative to the head bucket, clamped into [0, bmax - 1];
+// one block per distinct bucket present in the vector.
+__device__ __forceinline__ void l2_write(Ctx& c, uint64_t e, bool ok) {
+  uint64_t m = ballot(ok);
+  if (!m) return;
+  if (c.q.nrings == 1) {
+    l2_put_block(c, 0, e, ok, m);
+    return;
+  }
+  const uint32_t nr = c.q.nrings;
+  const uint32_t cur = uni(ld32(&c.q.ctrl->cur.v));
+  const uint32_t b = elem_d(e) >> c.q.d2_log2;
+  const uint32_t rel = b <= cur ? 0u : min(b - cur, nr - 1u);
+  const uint32_t ring = (cur + rel) & (nr - 1u);
+  while (m) {
+    const uint32_t r0 = lane_val(ring, first_lane(m));
+    const bool sel = ok && ring == r0;
+    const uint64_t ms = ballot(sel);
+    if (!l2_put_block(c, r0, e, sel, ms)) return;
+    ok = ok && !sel;
+    m &= ~ms;
+  }
+}
+
+// Take the block of ticket t of ring `ring` if it is published.
+__device__ __forceinline__ bool l2_take(Ctx& c, uint32_t ring, uint32_t t, uint64_t& e, bool& ok) {
+  const uint32_t nb = c.q.nb_log2;
+  const uint32_t slot = t & ((1u << nb) - 1u);
+  const uint32_t lap = t >> nb;
+  const uint64_t bidx = ((uint64_t)ring << nb) + slot;
+  uint64_t* h = c.q.hdr + bidx;
+  const uint64_t hv = uni64(ld64(h));
+  if ((uint32_t)(hv >> 32) != 2u * lap + 1u) return false;
+  const uint32_t k = (uint32_t)hv;
+  compiler_fence();
+  ok = lane() < k;
+  e = ok ? ld64(c.q.data + (bidx << 6) + lane()) : 0;
+  vm_drain();
+  if (lane() == 0) st64(h, (uint64_t)(2u * lap + 2u) << 32);
+  c.ct[kCtL2Reads] += 1;
+  return true;
+}
+
+// Read from one ring: keep a claimed ticket across READ_EMPTY (Section 4.2),
+// else claim the oldest unread one. With few blocks available the claim is a
+// compare-and-swap that never overshoots the writers; with many it is one
+// atomicAdd, whose rare overshoot leaves a pending claim for later.
+__device__ __forceinline__ bool l2_try_ring(Ctx& c, uint32_t ring, uint32_t t_seen, uint32_t h_seen, uint64_t& e,
+                                            bool& ok) {
+  uint32_t p = lane_val(c.pend, ring);
+  if (p == kInf) {
+    RingCtr* rc = c.q.rings + ring;
+    uint32_t claimed = 0;
+    if (lane() == 0) {
+      if ((int32_t)(t_seen - h_seen) > 64) {
+        p = add32(&rc->head.v, 1u);
+        claimed = 1;
+      } else {
+        uint32_t h = h_seen;
+        for (int i = 0; i < 4 && (int32_t)(t_seen - h) > 0; ++i) {
+          if (cas32(&rc->head.v, h, h + 1u)) {
+            p = h;
+            claimed = 1;
+            break;
+          }
+          h = ld32(&rc->head.v);
+          t_seen = ld32(&rc->tail.v);
+        }
+      }
+    }
+    if (!lane_val(claimed, 0)) return false;
+    p = lane_val(p, 0);
+  }
+  for (int i = 0; i < 4; ++i) {
+    if (l2_take(c, ring, p, e, ok)) {
+      if (lane() == ring) c.pend = kInf;
+      return true;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+  if (lane() == ring) c.pend = p;
+  return false;
+}
+
+// L2 Read.
+__device__ __forceinline__ bool l2_read(Ctx& c, uint64_t& e, bool& ok) {
+  if (c.q.nrings == 1) {
+    uint32_t t = 0, h = 0;
+    if (lane_val(c.pend, 0) == kInf) {
+      t = uni(ld32(&c.q.rings[0].tail.v));
+      h = uni(ld32(&c.q.rings[0].head.v));
+      if ((int32_t)(t - h) <= 0) return false;
+    }
+    return l2_try_ring(c, 0, t, h, e, ok);
+  }
+  // Bucket queue: lane i looks at bucket cur + i; scan the first bnum.
+  const uint32_t nr = c.q.nrings;
+  const uint32_t cur = uni(ld32(&c.q.ctrl->cur.v));
+  const bool in = lane() < nr;
+  const uint32_t r = (cur + lane()) & (nr - 1u);
+  uint32_t t = 0, h = 0;
+  if (in) {
+    t = ld32(&c.q.rings[r].tail.v);
+    h = ld32(&c.q.rings[r].head.v);
+  }
+  const uint32_t pend_r = __shfl(c.pend, (int)r);
+  const uint64_t m = ballot(in && (pend_r != kInf || (int32_t)(t - h) > 0));
+  // base moves to the first non-empty bucket when the head bucket is empty
+  if (m && !(m & 1u) && lane() == 0) cas32(&c.q.ctrl->cur.v, cur, cur + first_lane(m));
+  uint64_t mw = m & (c.q.bnum >= 64 ? ~0ull : ((1ull << c.q.bnum) - 1ull));
+  while (mw) {
+    const uint32_t j = first_lane(mw);
+    mw &= mw - 1;
+    if (l2_try_ring(c, (cur + j) & (nr - 1u), lane_val(t, j), lane_val(h, j), e, ok)) return true;
+  }
+  return false;
+}
+
+// ------------------------------------------------------------ grid-wide hub tier
+
+// A vertex of very high degree is not expanded by one wave: its edge range is
+// published as a record whose chunks any wave of the grid can claim.
+__device__ __forceinline__ void hub_post(Ctx& c, bool p, uint32_t v, uint32_t d, uint32_t beg, uint32_t end) {
+  QueryCtrl* ctl = c.q.ctrl;
+  const uint32_t ch = c.q.hub_chunk;
+  uint32_t r = kInf;
+  if (p) {
+    add32(&ctl->hub_units.v, (end - beg + ch - 1u) / ch);  // reserve before publishing
+    r = add32(&ctl->hub_tail.v, 1u);
+    if (r < c.q.hub_cap) {
+      st64(c.q.hub_rec + 2ull * r, make_elem(v, d));
+      st64(c.q.hub_rec + 2ull * r + 1, (uint64_t)beg | ((uint64_t)end << 32));
+    }
+  }
+  vm_drain();
+  if (p && r < c.q.hub_cap) st32(c.q.hub_pub + r, 1u);
+  if (ballot(p && r >= c.q.hub_cap)) fail(c, kStHubCapacity);
+}
+
+__device__ __forceinline__ bool hub_claim(Ctx& c, uint32_t& v, uint32_t& d, uint32_t& eb, uint32_t& ee) {
+  if (!c.q.th_hub) return false;
+  QueryCtrl* ctl = c.q.ctrl;
+  const uint32_t h = uni(ld32(&ctl->hub_head.v));
+  const uint32_t t = min(uni(ld32(&ctl->hub_tail.v)), c.q.hub_cap);
+  const uint32_t ch = c.q.hub_chunk;
+  for (uint32_t r = h; r < t && r < h + 8u; ++r) {
+    if (uni(ld32(c.q.hub_pub + r)) == 0) continue;
+    const uint64_t x0 = uni64(ld64(c.q.hub_rec + 2ull * r));
+    const uint64_t x1 = uni64(ld64(c.q.hub_rec + 2ull * r + 1));
+    const uint32_t beg = (uint32_t)x1, end = (uint32_t)(x1 >> 32);
+    const uint32_t nch = (end - beg + ch - 1u) / ch;
+    uint32_t ci = 0;
+    if (lane() == 0) ci = add32(c.q.hub_cur + r, 1u);
+    ci = lane_val(ci, 0);
+    if (ci < nch) {
+      v = elem_v(x0);
+      d = elem_d(x0);
+      eb = beg + ci * ch;
+      ee = min(end, eb + ch);
+      if (ci + 1u == nch && lane() == 0) cas32(&ctl->hub_head.v, r, r + 1u);
+      return true;
+    }
+    if (lane() == 0) cas32(&ctl->hub_head.v, r, r + 1u);
+  }
+  return false;
+}
+
+// ------------------------------------------------------------ L1 (LDS, private to the wave)
+
+// Near-far re-split (Section 3.4, L1NF): when near is empty, NF = min(far) +
+// delta1 and far elements below NF move to near; the rest is compacted in place.
+__device__ __forceinline__ void nf_resplit(Ctx& c) {
+  const uint32_t fh = c.fh, ft = c.ft;
+  const uint32_t cnt = ft - fh;
+  uint32_t mn = kInf;
+  for (uint32_t j = lane(); j < cnt; j += 64) mn = min(mn, elem_d(c.far[(fh + j) & c.l1mask]));
+  mn = uni(wave_min(mn));
+  const uint32_t nf = sat_add(mn, c.q.delta1);
+  uint32_t qt = c.qt, wp = fh;
+  for (uint32_t j = 0; j < cnt; j += 64) {
+    const bool has = j + lane() < cnt;
+    const uint64_t x = has ? c.far[(fh + j + lane()) & c.l1mask] : 0;
+    compiler_fence();
+    const bool tonear = has && elem_d(x) < nf;
+    const bool keep = has && !tonear;
+    const uint64_t m1 = ballot(tonear), m2 = ballot(keep);
+    if (tonear) c.l1[(qt + rank_of(m1)) & c.l1mask] = x;
+    if (keep) c.far[(wp + rank_of(m2)) & c.l1mask] = x;
+    compiler_fence();
+    qt += popc(m1);
+    wp += popc(m2);
+  }
+  c.thresh = nf;
+  c.qt = qt;
+  c.ft = wp;
+}
+
+__device__ __forceinline__ bool l1_empty(const Ctx& c) { return c.qh == c.qt && c.fh == c.ft; }
+
+// L1 Read: up to 64 elements, near ring first.
+__device__ __forceinline__ bool l1_take(Ctx& c, uint64_t& e, bool& ok) {
+  if (c.q.l1_type == MLMQ_L1_NEARFAR && c.qt == c.qh && c.ft != c.fh) nf_resplit(c);
+  const uint32_t k = min(c.qt - c.qh, 64u);
+  ok = lane() < k;
+  e = ok ? c.l1[(c.qh + lane()) & c.l1mask] : 0;
+  compiler_fence();
+  c.qh += k;
+  return k != 0;
+}
+
+// L1 Write. Lanes that must go to L2 come back in `spill`.
+// Returns true when an L1V periodic flush is due.
+__device__ __forceinline__ bool l1_put(Ctx& c, uint64_t e, bool ok, bool& spill) {
+  const uint32_t cap = c.q.l1_cap;
+  const uint32_t d = elem_d(e);
+  if (c.q.l1_type == MLMQ_L1_NEARFAR) {
+    const bool np = ok && d < c.thresh;
+    const bool fp = ok && !np;
+    const uint64_t mn = ballot(np), mf = ballot(fp);
+    const uint32_t sn = cap - (c.qt - c.qh), sf = cap - (c.ft - c.fh);
+    const uint32_t rn = rank_of(mn), rf = rank_of(mf);
+    if (np && rn < sn) c.l1[(c.qt + rn) & c.l1mask] = e;
+    if (fp && rf < sf) c.far[(c.ft + rf) & c.l1mask] = e;
+    compiler_fence();
+    spill = (np && rn >= sn) || (fp && rf >= sf);
+    c.qt += min(popc(mn), sn);
+    c.ft += min(popc(mf), sf);
+    return false;
+  }
+  bool keep = ok;
+  spill = false;
+  if (c.q.l1_type == MLMQ_L1_FILTER) {
+    keep = ok && d <= c.thresh;
+    spill = ok && !keep;
+  }
+  const uint64_t m = ballot(keep);
+  const uint32_t space = cap - (c.qt - c.qh);
+  const uint32_t r = rank_of(m);
+  if (keep && r < space) c.l1[(c.qt + r) & c.l1mask] = e;
+  compiler_fence();
+  spill = spill || (keep && r >= space);
+  c.qt += min(popc(m), space);
+  if (c.q.l1_type == MLMQ_L1_VEC && c.q.l1_wb) {
+    if (++c.wcount >= c.q.l1_wb) {
+      c.wcount = 0;
+      return true;
+    }
+  }
+  return false;
+}
+
+// L1V periodic flush: everything currently in L1 goes back to L2.
+__device__ __forceinline__ void l1_flush(Ctx& c) {
+  c.ct[kCtFlushes] += 1;
+  while (c.qt != c.qh && !c.stop) {
+    uint64_t x = 0;
+    bool ok = false;
+    l1_take(c, x, ok);
+    l2_write(c, x, ok);
+  }
+}
+
+// Write cascade below L0: L1, whose overflow goes to L2.
+__device__ __forceinline__ void write_l1(Ctx& c, uint64_t e, bool ok) {
+  if (c.q.l1_type == MLMQ_L1_NONE) {
+    l2_write(c, e, ok);
+    return;
+  }
+  bool spill = false;
+  const bool flush = l1_put(c, e, ok, spill);
+  c.ct[kCtL1Writes] += 1;
+  if (ballot(spill)) l2_write(c, e, spill);
+  if (flush) l1_flush(c);
+}
+
+// L0 full: all of its elements move to L1 (Section 3.4, L0 queue).
+__device__ __forceinline__ void spill_l0(Ctx& c) {
+  while (c.l0n && !c.stop) {
+    uint64_t x;
+    bool ok;
+    l0_read(c, x, ok);
+    write_l1(c, x, ok);
+  }
+}
+
+// Unified Write of the lanes' new work items (after wave compaction).
+__device__ __forceinline__ void emit(Ctx& c, uint32_t v, uint32_t nd, bool imp) {
+  const uint64_t m = ballot(imp);
+  if (!m) return;
+  const uint32_t k = popc(m);
+  c.ct[kCtPushes] += k;
+  const uint64_t e = make_elem(v, nd);
+  if (c.q.l0_cap) {
+    if (c.l0n + k > c.q.l0_cap) spill_l0(c);
+    stage(c, e, imp);
+    l0_append(c, k);
+  } else {
+    write_l1(c, e, imp);
+  }
+}
+
+// ------------------------------------------------------------ relaxation
+
+// Relax one edge per lane (the relax step of the paper's kernel sketch, with
+// atomicMin): candidate nd = d + w; a plain load of dist[v] filters hopeless
+// candidates, then atomicMin decides; the lane has new work iff nd < the
+// previous label.
+__device__ __forceinline__ void relax_emit(Ctx& c, bool has, uint32_t ed, uint32_t d) {
+  uint32_t v = 0, nd = 0;
+  bool imp = false, of = false;
+  if (has) {
+    const uint64_t a = c.q.adj[ed];
+    v = (uint32_t)a;
+    const uint64_t s = (uint64_t)d + (a >> 32);
+    if (s >= kInf) {
+      of = true;
+    } else {
+      nd = (uint32_t)s;
+      if (nd < ld_label(c.q.dist + v)) {
+        const uint32_t old = __hip_atomic_fetch_min(c.q.dist + v, nd, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        imp = nd < old;
+      }
+    }
+  }
+  c.ct[kCtEdges] += popc(ballot(has));
+  if (ballot(of)) c.ovf = true;
+  emit(c, v, nd, imp);
+}
+
+// Whole wave sweeps the edge range [eb, ee) of one vertex.
+__device__ __forceinline__ void process_range(Ctx& c, uint32_t d, uint32_t eb, uint32_t ee) {
+  for (uint32_t x = eb; x < ee && !c.stop; x += 64) relax_emit(c, x + lane() < ee, x + lane(), d);
+}
+
+// Relaxation of a batch (the paper's SSSP_relax with the load balancing of
+// Section 4.1): drop stale items, send very-high-degree vertices to the
+// grid-wide tier, let the whole wave sweep vertices above th_v, and spread the
+// edges of the remaining vertices evenly over the lanes.
+__device__ __forceinline__ void process_vec(Ctx& c, uint64_t e, bool ok) {
+  const uint32_t v = elem_v(e), d = elem_d(e);
+  const bool stale = ok && d > ld_label(c.q.dist + v);
+  c.ct[kCtStale] += popc(ballot(stale));
+  ok = ok && !stale;
+  c.ct[kCtExpansions] += popc(ballot(ok));
+  uint32_t beg = 0, end = 0;
+  if (ok) {
+    beg = (uint32_t)c.q.off[v];
+    end = (uint32_t)c.q.off[v + 1];
+  }
+  const uint32_t deg = end - beg;
+  if (c.q.th_hub) {
+    const bool hub = ok && deg > c.q.th_hub;
+    if (ballot(hub)) {
+      hub_post(c, hub, v, d, beg, end);
+      ok = ok && !hub;
+      if (c.stop) return;
+    }
+  }
+  const bool big = ok && deg > c.q.th_v;
+  const uint32_t sdeg = (ok && !big) ? deg : 0u;
+  const uint32_t incl = wave_incl_scan(sdeg);
+  const uint32_t total = lane_val(incl, 63);
+  const uint32_t excl = incl - sdeg;
+  for (uint32_t base = 0; base < total && !c.stop; base += 64) {
+    const uint32_t idx = base + lane();
+    uint32_t j = 0;
+#pragma unroll
+    for (uint32_t st = 32; st; st >>= 1) {
+      if ((uint32_t)__shfl(incl, (int)(j + st - 1)) <= idx) j += st;
+    }
+    const uint32_t ed = (uint32_t)__shfl(beg, (int)j) + (idx - (uint32_t)__shfl(excl, (int)j));
+    relax_emit(c, idx < total, ed, (uint32_t)__shfl(d, (int)j));
+  }
+  uint64_t mb = ballot(big);
+  while (mb && !c.stop) {
+    const uint32_t j = first_lane(mb);
+    mb &= mb - 1;
+    process_range(c, lane_val(d, j), lane_val(beg, j), lane_val(end, j));
+  }
+}
+
+// ------------------------------------------------------------ termination
+
+// Delayed-count emptiness test (Section 4.1): read done first, then the
+// reservations; equality means no work existed when done was read.
+__device__ __forceinline__ bool try_terminate(Ctx& c) {
+  QueryCtrl* ctl = c.q.ctrl;
+  const uint32_t done = uni(ld32(&ctl->done.v));
+  vm_drain();
+  const uint32_t t = lane() < c.q.nrings ? ld32(&c.q.rings[lane()].tail.v) : 0u;
+  const uint32_t units = c.q.th_hub ? uni(ld32(&ctl->hub_units.v)) : 0u;
+  const uint32_t reserved = uni(wave_sum(t)) + units;
+  if (done == reserved) {
+    if (lane() == 0) st32(&ctl->terminate.v, 1u);
+    return true;
+  }
+  return false;
+}
+
+// Threshold of the filter queue after taking a batch whose smallest distance
+// is mn (our reading: F = min + delta1 on every refill from the global levels).
+__device__ __forceinline__ void refill_threshold(Ctx& c, uint32_t mn) {
+  if (c.q.l1_type == MLMQ_L1_FILTER) c.thresh = sat_add(mn, c.q.delta1);
+}
+
+// The persistent worker loop of one wave on one query (the paper's work
+// kernel with the manager's emptiness test folded in).
+__device__ __forceinline__ void run_query(Ctx& c) {
+  uint32_t idle = 0;
+  while (!c.stop) {
+    ++c.it;
+    beat(c.beat, kPtLoop, c.it);
+    if ((c.it & 63u) == 0 && must_stop(c)) break;
+    uint64_t e = 0;
+    bool ok = false, got = false;
+    if (c.l0n) {
+      l0_read(c, e, ok);
+      got = true;
+    } else if (c.q.l1_type != MLMQ_L1_NONE && !l1_empty(c)) {
+      got = l1_take(c, e, ok);
+      c.ct[kCtL1Reads] += 1;
+    } else {
+      uint32_t hv, hd, heb, hee;
+      beat(c.beat, kPtHub, c.it);
+      if (hub_claim(c, hv, hd, heb, hee)) {
+        c.done_acc += 1u;
+        refill_threshold(c, hd);
+        c.ct[kCtHubChunks] += 1;
+        idle = 0;
+        if (hd <= uni(ld_label(c.q.dist + hv))) process_range(c, hd, heb, hee);
+        continue;
+      }
+      beat(c.beat, kPtL2Read, c.it);
+      got = l2_read(c, e, ok);
+      if (got) {
+        c.done_acc += 1u;
+        refill_threshold(c, uni(wave_min(ok ? elem_d(e) : kInf)));
+      } else {
+        // Idle: the wave holds nothing, so its delayed count can go out.
+        beat(c.beat, kPtIdle, c.it);
+        if (c.done_acc) {
+          uint32_t r = 0;
+          if (lane() == 0) r = add32(&c.q.ctrl->done.v, c.done_acc);
+          (void)lane_val(r, 0);
+          vm_drain();
+          c.done_acc = 0;
+        }
+        if (try_terminate(c)) break;
+        if ((++idle & 7u) == 0 && must_stop(c)) break;
+        backoff(min(idle >> 2, 6u));
+        continue;
+      }
+    }
+    idle = 0;
+    beat(c.beat, kPtProcess, c.it);
+    process_vec(c, e, ok);
+  }
+  beat(c.beat, kPtDone, c.it);
+}
+
+// Next query for this wave: queries are taken in order; each accepts up to
+// want_wgs workgroups over its lifetime.
+__device__ __forceinline__ uint32_t pick_query(const LaunchArgs& a) {
+  uint32_t q = kInf;
+  if (lane() == 0 && ld32(&a.batch->cancel.v) == 0) {
+    for (uint32_t i = ld32(&a.batch->cursor.v); i < (uint32_t)a.nq; ++i) {
+      const QueryDesc* d = a.queries + i;
+      if (ld32(&d->ctrl->terminate.v) == 0 && add32(&d->ctrl->joined.v, 1u) < d->want_wgs) {
+        q = i;
+        break;
+      }
+      cas32(&a.batch->cursor.v, i, i + 1);
+    }
+  }
+  return lane_val(q, 0);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ kernels
+
+// One wave per workgroup; dynamic LDS = staging row + L1 ring(s).
+__global__ void __launch_bounds__(64) mlmq_worker(LaunchArgs a) {
+  extern __shared__ uint64_t smem[];
+  const uint64_t t0 = (uint64_t)wall_clock64();
+  uint32_t* const my_beat = a.beats ? a.beats + blockIdx.x : nullptr;
+  for (;;) {
+    beat(my_beat, kPtPick, 0);
+    const uint32_t qi = pick_query(a);
+    if (qi == kInf) break;
+    Ctx c;
+    c.q = a.queries[qi];
+    c.stg = smem;
+    c.l1 = smem + 64;
+    c.far = c.l1 + a.l1_cap;
+    c.l1mask = c.q.l1_cap - 1u;
+    c.qh = c.qt = c.fh = c.ft = 0;
+    c.thresh = c.q.l1_type == MLMQ_L1_FILTER ? c.q.delta1 : 0u;
+    c.wcount = 0;
+    c.done_acc = 0;
+    c.pend = kInf;
+    c.cancel = &a.batch->cancel.v;
+    c.deadline = t0 + a.timeout_ticks;
+    c.cap_wait = a.cap_wait_ticks;
+    c.r0 = c.r1 = c.r2 = c.r3 = 0;
+    c.l0h = c.l0n = 0;
+    c.beat = my_beat;
+    c.it = 0;
+    c.stop = false;
+    c.ovf = false;
+#pragma unroll
+    for (int i = 0; i < kNumCounters; ++i) c.ct[i] = 0;
+    run_query(c);
+    if (lane() == 0) {
+      QueryCtrl* ctl = c.q.ctrl;
+#pragma unroll
+      for (int i = 0; i < kNumCounters; ++i)
+        if (c.ct[i]) __hip_atomic_fetch_add(&ctl->stats[i], (uint64_t)c.ct[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (c.ovf) st32(&ctl->overflow.v, 1u);
+      add32(&ctl->finished.v, 1u);
+    }
+  }
+}
+
+// Per-query reset: dist = UINT32_MAX except dist[source] = 0, all L2 slots
+// free except ring 0 / slot 0, which holds the source (it is written through
+// to L2 before the worker starts, Section 4.1), counters zero, reservation 1.
+__global__ void mlmq_init(const QueryDesc* qs, BatchCtrl* batch) {
+  const QueryDesc& q = qs[blockIdx.y];
+  const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t stride = gridDim.x * blockDim.x;
+  if (blockIdx.y == 0 && tid == 0) {
+    batch->cursor.v = 0;
+    batch->cancel.v = 0;
+  }
+  const uint32_t n = q.n, src = q.source;
+  uint32_t* dist = q.dist;
+  for (uint32_t i = tid; i < n; i += stride) dist[i] = i == src ? 0u : kInf;
+  const uint32_t nh = q.nrings << q.nb_log2;
+  uint64_t* hdr = q.hdr;
+  for (uint32_t i = tid; i < nh; i += stride) hdr[i] = i == 0 ? ((1ull << 32) | 1ull) : 0ull;
+  const uint32_t hc = q.hub_cap;
+  for (uint32_t i = tid; i < hc; i += stride) {
+    q.hub_cur[i] = 0;
+    q.hub_pub[i] = 0;
+  }
+  for (uint32_t i = tid; i < q.nrings; i += stride) {
+    q.rings[i].tail.v = i == 0 ? 1u : 0u;
+    q.rings[i].head.v = 0;
+  }
+  const uint32_t cw = sizeof(QueryCtrl) / 4;
+  uint32_t* cwp = reinterpret_cast<uint32_t*>(q.ctrl);
+  for (uint32_t i = tid; i < cw; i += stride) cwp[i] = 0;
+  if (tid == 0) q.data[0] = make_elem(src, 0);
+}
+
+// Overflow test (exact): some reachable vertex has a distance >= 2^32 - 1 iff
+// an edge leaves a finite label towards an unreachable one.
+__global__ void mlmq_overflow_check(const QueryDesc* qs, uint32_t* flag) {
+  const QueryDesc& q = qs[0];
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < q.n; u += stride) {
+    if (q.dist[u] == kInf) continue;
+    for (int32_t e = q.off[u]; e < q.off[u + 1]; ++e)
+      if (q.dist[(uint32_t)q.adj[e]] == kInf) {
+        *flag = 1u;
+        break;
+      }
+  }
+}
+
+// Copy every query's status word, overflow flag and counters into one array.
+__global__ void mlmq_gather(const QueryDesc* qs, int nq, QueryResult* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nq) return;
+  const QueryCtrl* ctl = qs[i].ctrl;
+  out[i].error = ctl->error.v;
+  out[i].overflow = ctl->overflow.v;
+  for (int k = 0; k < kNumCounters; ++k) out[i].stats[k] = ctl->stats[k];
+}
+
+// ------------------------------------------------------------ host launchers
+
+size_t worker_lds_bytes(uint32_t waves, uint32_t l1_cap, bool two_rings) {
+  (void)waves;
+  return 8ull * (64ull + (uint64_t)l1_cap * (two_rings ? 2u : 1u));
+}
+
+hipError_t launch_init(const QueryDesc* d_queries, BatchCtrl* d_batch, int nq, uint32_t max_words, hipStream_t s) {
+  uint32_t blocks = (max_words + 255u) / 256u;
+  blocks = blocks < 1u ? 1u : (blocks > 2048u ? 2048u : blocks);
+  hipLaunchKernelGGL(mlmq_init, dim3(blocks, (uint32_t)nq), dim3(256), 0, s, d_queries, d_batch);
+  return hipGetLastError();
+}
+
+hipError_t launch_worker(const LaunchArgs& a, uint32_t grid, uint32_t wg_size, size_t lds, hipStream_t s) {
+  hipLaunchKernelGGL(mlmq_worker, dim3(grid), dim3(wg_size), lds, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_overflow_check(const QueryDesc* d_query, uint32_t* d_flag, hipStream_t s) {
+  hipLaunchKernelGGL(mlmq_overflow_check, dim3(1024), dim3(256), 0, s, d_query, d_flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather(const QueryDesc* d_queries, int nq, QueryResult* d_out, hipStream_t s) {
+  hipLaunchKernelGGL(mlmq_gather, dim3((uint32_t)(nq + 255) / 256u), dim3(256), 0, s, d_queries, nq, d_out);
+  return hipGetLastError();
+}
+
+hipError_t worker_occupancy(uint32_t wg_size, size_t lds, int* wgs_per_cu) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(wgs_per_cu, mlmq_worker, (int)wg_size, lds);
+}
+
+}  // namespace mlmq

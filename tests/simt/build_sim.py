@@ -1,0 +1,49 @@
+"""Compile the library's kernel source for the CPU (tests only).
+
+The HIP kernel file is rewritten mechanically -- the dynamic LDS array becomes
+the emulated workgroup's buffer, inline assembly (waits and compiler fences)
+becomes a wave reconvergence barrier, the HIP launch wrappers are dropped --
+and compiled with g++ against hip/hip_runtime.h from this directory.
+"""
+import os
+import re
+import subprocess
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+CSRC = os.path.join(ROOT, "paper_2602_10080_amd", "csrc")
+KERNEL = os.path.join(CSRC, "mlmq_kernels.hip")
+
+
+def transformed_source(checked: bool = False) -> str:
+    src = open(KERNEL).read()
+    if checked:
+        # bounds-check every edge and vertex index the kernel dereferences
+        src = src.replace("c.q.adj[ed]", "c.q.adj[simt_chk(ed, (uint64_t)c.q.off[c.q.n], \"adj\", __LINE__)]")
+        src = src.replace("c.q.off[v]", "c.q.off[simt_chk(v, c.q.n, \"off\", __LINE__)]")
+        src = src.replace("c.q.dist + v", "c.q.dist + simt_chk(v, c.q.n, \"dist\", __LINE__)")
+        src = src.replace("c.q.dist + hv", "c.q.dist + simt_chk(hv, c.q.n, \"dist\", __LINE__)")
+    src = src.replace("extern __shared__ uint64_t smem[];",
+                      "uint64_t* smem = reinterpret_cast<uint64_t*>(simt::group->lds);")
+    src = re.sub(r'asm volatile\("([^"]*)"\s*:::\s*"memory"\);', lambda mo: 'simt::wave_sync_at("asm ' + mo.group(1) + '");', src)
+    cut = src.index("hipError_t launch_init(")
+    return src[:cut] + "\n}  // namespace mlmq\n"
+
+
+def build(out_dir: str, sanitize: bool = False, checked: bool = True) -> str:
+    os.makedirs(out_dir, exist_ok=True)
+    inc = os.path.join(out_dir, "sim_kernels.inc")
+    with open(inc, "w") as f:
+        f.write(transformed_source(checked))
+    lib = os.path.join(out_dir, "libsim%s.so" % ("_asan" if sanitize else ""))
+    cmd = ["g++", "-std=c++20", "-O1", "-g", "-fPIC", "-shared", "-pthread", "-w",
+           "-I", HERE, "-iquote", CSRC, "-iquote", out_dir,
+           os.path.join(HERE, "harness.cpp"), "-o", lib]
+    if sanitize:
+        cmd[1:1] = ["-fsanitize=address,undefined", "-fno-omit-frame-pointer"]
+    subprocess.check_call(cmd)
+    return lib
+
+
+if __name__ == "__main__":
+    print(build(os.path.join(ROOT, "_work", "sim")))

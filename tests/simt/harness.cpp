@@ -1,0 +1,166 @@
+// Runs the library's init and persistent worker kernels on the CPU (one host
+// thread per lane) for small graphs. Test infrastructure only.
+#include <cstdio>
+#include <cstdlib>
+#include <vector>
+
+#include "sim_kernels.inc"
+
+namespace simt {
+thread_local unsigned lane;
+thread_local Wave* wave;
+thread_local Group* group;
+thread_local dim3 tidx, bidx, bdim, gdim;
+thread_local uint64_t nops;
+bool check_stacks = getenv("SIM_STACKS") != nullptr;
+}  // namespace simt
+
+using namespace mlmq;
+
+namespace {
+// Device memory and LDS start with whatever was there before; mimic that
+// with a fixed garbage pattern unless SIM_ZERO is set.
+template <class T>
+T* zalloc(size_t count) {
+  void* p = nullptr;
+  const size_t bytes = sizeof(T) * (count ? count : 1);
+  if (posix_memalign(&p, 256, bytes)) abort();
+  if (getenv("SIM_ZERO")) {
+    std::memset(p, 0, bytes);
+  } else {
+    uint64_t x = 0x9E3779B97F4A7C15ull ^ bytes;
+    uint8_t* b = static_cast<uint8_t*>(p);
+    for (size_t i = 0; i < bytes; ++i) {
+      x ^= x << 13;
+      x ^= x >> 7;
+      x ^= x << 17;
+      b[i] = (uint8_t)x;
+    }
+  }
+  return static_cast<T*>(p);
+}
+}  // namespace
+
+// knobs: l0_rows, l1_type, l2_type, l1_cap, l1_wb, delta1, d2_log2, bmax, bnum,
+//        th_v, th_hub, hub_chunk, nb_log2, hub_cap, timeout_ms
+extern "C" int sim_sssp(int32_t n, const int32_t* off, const int32_t* col, const uint32_t* w, uint32_t src,
+                        uint32_t* dist, const uint32_t* k, uint32_t nwg, uint32_t wg_size, uint64_t* stats,
+                        uint32_t* status) {
+  const int64_t m = off[n];
+  std::vector<uint64_t> adj((size_t)m + 1);
+  for (int64_t e = 0; e < m; ++e) adj[e] = (uint32_t)col[e] | ((uint64_t)w[e] << 32);
+  const uint32_t nrings = k[2] == 1 ? k[7] : 1;
+  const uint32_t nb_log2 = k[12], hub_cap = k[13];
+  const uint64_t nh = (uint64_t)nrings << nb_log2;
+  QueryCtrl* ctrl = zalloc<QueryCtrl>(1);
+  RingCtr* rings = zalloc<RingCtr>(nrings);
+  uint64_t* hdr = zalloc<uint64_t>(nh);
+  uint64_t* data = zalloc<uint64_t>(nh * 64);
+  uint64_t* hub_rec = zalloc<uint64_t>(2ull * hub_cap);
+  uint32_t* hub_cur = zalloc<uint32_t>(hub_cap);
+  uint32_t* hub_pub = zalloc<uint32_t>(hub_cap);
+  BatchCtrl* batch = zalloc<BatchCtrl>(1);
+  QueryDesc* q = zalloc<QueryDesc>(1);
+  q->off = off;
+  q->adj = adj.data();
+  q->dist = dist;
+  q->ctrl = ctrl;
+  q->rings = rings;
+  q->hdr = hdr;
+  q->data = data;
+  q->hub_rec = hub_rec;
+  q->hub_cur = hub_cur;
+  q->hub_pub = hub_pub;
+  q->n = (uint32_t)n;
+  q->source = src;
+  q->nb_log2 = nb_log2;
+  q->nrings = nrings;
+  q->hub_cap = hub_cap;
+  q->l0_cap = 64u * k[0];
+  q->l1_type = k[1];
+  q->l2_type = k[2];
+  q->l1_cap = k[1] == MLMQ_L1_NONE ? 64u : k[3];
+  q->l1_wb = k[4];
+  q->delta1 = k[5];
+  q->d2_log2 = k[6];
+  q->bnum = k[2] == 1 ? k[8] : 1;
+  q->th_v = k[9];
+  q->th_hub = k[10];
+  q->hub_chunk = k[11];
+  q->want_wgs = nwg;
+  // init kernel, serially over its threads (it has no cross-lane operations)
+  const uint32_t blocks = 4;
+  simt::gdim = dim3(blocks, 1);
+  simt::bdim = dim3(256);
+  for (uint32_t b = 0; b < blocks; ++b)
+    for (uint32_t t = 0; t < 256; ++t) {
+      simt::bidx = dim3(b, 0);
+      simt::tidx = dim3(t);
+      mlmq_init(q, batch);
+    }
+  // persistent worker: nwg workgroups x wg_size lane threads
+  const uint32_t waves = wg_size / 64;
+  const uint32_t l1cap = q->l1_cap;
+  const bool two = k[1] == MLMQ_L1_NEARFAR;
+  const size_t lds = worker_lds_bytes(waves, l1cap, two);
+  LaunchArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.queries = q;
+  a.batch = batch;
+  a.nq = 1;
+  a.l1_cap = l1cap;
+  a.l1_two = two;
+  a.waves = waves;
+  a.timeout_ticks = (uint64_t)k[14] * 100000ull;
+  a.cap_wait_ticks = 200ull * 100000ull;
+  a.beats = nullptr;
+  std::vector<simt::Wave*> wv;
+  std::vector<simt::Group> grp(nwg);
+  std::vector<std::barrier<>*> bars;
+  std::vector<uint8_t*> ldsb;
+  for (uint32_t g = 0; g < nwg; ++g) {
+    bars.push_back(new std::barrier<>(wg_size));
+    ldsb.push_back(zalloc<uint8_t>(lds));
+    grp[g].bar = bars.back();
+    grp[g].lds = ldsb.back();
+    for (uint32_t w2 = 0; w2 < waves; ++w2) wv.push_back(new simt::Wave());
+  }
+  std::vector<std::thread> th;
+  for (uint32_t g = 0; g < nwg; ++g)
+    for (uint32_t t = 0; t < wg_size; ++t)
+      th.emplace_back([&, g, t] {
+        simt::lane = t % 64;
+        simt::nops = 0;
+        simt::wave = wv[g * waves + t / 64];
+        simt::group = &grp[g];
+        simt::tidx = dim3(t);
+        simt::bidx = dim3(g);
+        simt::bdim = dim3(wg_size);
+        simt::gdim = dim3(nwg);
+        mlmq_worker(a);
+      });
+  for (auto& t : th) t.join();
+  if (getenv("SIM_DUMP"))
+    fprintf(stderr, "ring0 tail %u head %u done %u term %u err %u\n", rings[0].tail.v, rings[0].head.v,
+            ctrl->done.v, ctrl->terminate.v, ctrl->error.v);
+  for (int i = 0; i < kNumCounters && stats; ++i) stats[i] = ctrl->stats[i];
+  if (status) {
+    status[0] = ctrl->error.v;
+    status[1] = ctrl->overflow.v;
+    status[2] = ctrl->done.v;
+    status[3] = rings[0].tail.v;
+  }
+  for (auto* p : wv) delete p;
+  for (auto* p : bars) delete p;
+  for (auto* p : ldsb) free(p);
+  free(ctrl);
+  free(rings);
+  free(hdr);
+  free(data);
+  free(hub_rec);
+  free(hub_cur);
+  free(hub_pub);
+  free(batch);
+  free(q);
+  return 0;
+}

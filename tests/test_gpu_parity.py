@@ -1,0 +1,191 @@
+"""GPU parity: every queue configuration, on graphs that exercise several
+tiles, ragged tails and the degenerate cases, must give the oracle's
+distance vector bit for bit (integer arithmetic, tolerance 0)."""
+import sys
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+INF = oracle.UNREACHABLE
+
+
+def _mlmq():
+    import paper_2602_10080_amd as mlmq
+    return mlmq
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+CONFIGS = {
+    "L0x2-L1V-L2V": dict(l0_rows=2, l1_type=1, l2_type=0, l1_flush_wb=64, th_hub=0),
+    "L0off-L1none-L2V": dict(l0_rows=0, l1_type=0, l2_type=0, th_hub=0),
+    "L0x1-L1none-L2V": dict(l0_rows=1, l1_type=0, l2_type=0, th_hub=0),
+    "L0x4-L1V-L2V-wb4": dict(l0_rows=4, l1_type=1, l2_type=0, l1_flush_wb=4, l1_cap=256, th_hub=0),
+    "L0x1-L1NF-L2V": dict(l0_rows=1, l1_type=2, l2_type=0, delta1=64, th_hub=0),
+    "L0x1-L1FQ-L2V": dict(l0_rows=1, l1_type=3, l2_type=0, delta1=64, th_hub=0),
+    "L0x2-L1V-L2DQ": dict(l0_rows=2, l1_type=1, l2_type=1, bmax=16, bnum=4, delta2_log2=6, th_hub=0),
+    "L0x1-L1NF-L2DQ": dict(l0_rows=1, l1_type=2, l2_type=1, bmax=32, bnum=2, delta2_log2=5, delta1=32,
+                           th_hub=0),
+    "L0x1-L1FQ-L2DQ-hub": dict(l0_rows=1, l1_type=3, l2_type=1, bmax=8, bnum=8, delta2_log2=8, delta1=128,
+                               th_hub=128, hub_chunk=128),
+    "L0x2-L1V-L2V-hub64": dict(l0_rows=2, l1_type=1, l2_type=0, th_v=8, th_hub=64, hub_chunk=64),
+    "L0x1-L1V-cap64": dict(l0_rows=1, l1_type=1, l2_type=0, l1_cap=64, th_hub=0),
+    "L0x2-L1NF-L2DQ-b64": dict(l0_rows=2, l1_type=2, l2_type=1, bmax=64, bnum=8, th_hub=0),
+    "grid8-L1V-L2V": dict(l0_rows=2, l1_type=1, l2_type=0, grid_wgs=8, th_hub=0),
+    "tinyL2-L1none": dict(l0_rows=0, l1_type=0, l2_type=0, l2_capacity=1024, th_hub=0),
+}
+
+
+def _graphs():
+    rng = np.random.default_rng(5)
+    out = {}
+    out["grid64"] = (gg.grid(64, 64, 0.0, seed=1), 0)
+    out["road96x80"] = (gg.grid(96, 80, 0.1, seed=2), 40 * 80 + 33)
+    out["rmat12"] = (g := gg.rmat(12, 8, seed=3), gg.max_degree_vertex(g))
+    out["uniform"] = (gg.uniform(5000, 40000, wmax=65535, seed=4), 17)
+    n = 3000
+    out["path"] = (gg.from_edges(n, np.arange(n - 1), np.arange(1, n), rng.integers(0, 300, n - 1)), 0)
+    leaves = np.arange(1, 2001)
+    w = rng.integers(1, 256, 2000)
+    out["star"] = (gg.from_edges(2001, np.concatenate([np.zeros(2000, int), leaves]),
+                                 np.concatenate([leaves, np.zeros(2000, int)]), np.concatenate([w, w])), 0)
+    out["isolated_src"] = (gg.from_edges(100, np.arange(1, 99), np.arange(2, 100), np.ones(98)), 0)
+    z = gg.rmat(11, 8, seed=6)
+    z.w[:] = 0
+    out["zero_w"] = (z, gg.max_degree_vertex(z))
+    out["multi"] = (gg.random_small(500, 6000, 9, rng, wmin=0), 3)
+    big = gg.grid(40, 40, 0.0, seed=8)
+    big.w[:] = (2**32 - 10) // 100
+    out["near_overflow"] = (big, 0)
+    return out
+
+
+GRAPHS = _graphs()
+
+
+@pytest.fixture(scope="module")
+def dev_graphs():
+    mlmq = _mlmq()
+    return {k: (mlmq.Graph.from_csr(csr), csr, s) for k, (csr, s) in GRAPHS.items()}
+
+
+@pytest.fixture(scope="module")
+def oracle_dist():
+    return {k: oracle.dijkstra(csr, s) for k, (csr, s) in GRAPHS.items()}
+
+
+@pytest.mark.parametrize("cfg_name", list(CONFIGS))
+@pytest.mark.parametrize("graph_name", list(GRAPHS))
+def test_parity(dev_graphs, oracle_dist, graph_name, cfg_name):
+    mlmq = _mlmq()
+    g, csr, src = dev_graphs[graph_name]
+    _say(f"[parity] graph={graph_name} n={csr.n} m={csr.m} src={src} cfg={cfg_name}")
+    cfg = mlmq.default_config(**CONFIGS[cfg_name], timeout_ms=20000)
+    try:
+        out, st = mlmq.sssp(g, src, config=cfg, stats=True)
+    except mlmq.MlmqError as e:
+        # a deliberately tiny L2 may run out of room even after its retries;
+        # that must surface as a capacity error, never a hang or a wrong answer
+        if cfg_name.startswith("tinyL2") and e.code == mlmq.ERR_QUEUE_CAPACITY:
+            return
+        raise
+    torch.cuda.synchronize()
+    got = mlmq.to_numpy(out)
+    want = oracle_dist[graph_name]
+    bad = np.nonzero(got != want)[0]
+    assert bad.size == 0, f"{bad.size} mismatches, first at {bad[:5]}: got {got[bad[:5]]} want {want[bad[:5]]}"
+    n_reach, _ = oracle.reach_stats(csr, want)
+    assert st["expansions"] >= n_reach
+    assert st["status"] == 0
+
+
+def test_repeat_same_buffer(dev_graphs, oracle_dist):
+    """Solves from different sources into one reused buffer: nothing stale leaks."""
+    mlmq = _mlmq()
+    g, csr, _ = dev_graphs["road96x80"]
+    out = mlmq.new_dist(csr.n)
+    for src in (0, 5000, 7679, 123):
+        _say(f"[repeat] src={src}")
+        mlmq.sssp(g, src, out=out, config=mlmq.default_config(th_hub=0))
+        torch.cuda.synchronize()
+        assert np.array_equal(mlmq.to_numpy(out), oracle.dijkstra(csr, src))
+
+
+def test_host_output_buffer(dev_graphs, oracle_dist):
+    mlmq = _mlmq()
+    g, csr, src = dev_graphs["rmat12"]
+    out = np.empty(csr.n, dtype=np.uint32)
+    mlmq.sssp(g, src, out=out)
+    assert np.array_equal(out, oracle_dist["rmat12"])
+
+
+def test_golden_example(golden):
+    mlmq = _mlmq()
+    n, src, edges, expect = golden("redundant_wavefront.txt")
+    u, v, w = zip(*edges)
+    csr = gg.from_edges(n, u, v, w)
+    g = mlmq.Graph.from_csr(csr)
+    for name, kw in CONFIGS.items():
+        out = mlmq.sssp(g, src, config=mlmq.default_config(**kw))
+        torch.cuda.synchronize()
+        got = mlmq.to_numpy(out)
+        assert {i: int(got[i]) for i in range(n)} == expect, name
+
+
+def test_overflow_reported():
+    mlmq = _mlmq()
+    big = 2**31
+    csr = gg.from_edges(4, [0, 1, 2], [1, 2, 3], [big, big - 1, 5])
+    g = mlmq.Graph.from_csr(csr)
+    with pytest.raises(mlmq.MlmqError) as ei:
+        mlmq.sssp(g, 0)
+    assert ei.value.code == mlmq.ERR_DISTANCE_OVERFLOW
+    # exactly 2^32 - 2 is representable
+    csr = gg.from_edges(3, [0, 1], [1, 2], [big, big - 2])
+    g = mlmq.Graph.from_csr(csr)
+    got = mlmq.to_numpy(mlmq.sssp(g, 0))
+    assert got.tolist() == [0, big, 2**32 - 2]
+
+
+def test_invalid_arguments():
+    mlmq = _mlmq()
+    csr = gg.grid(8, 8)
+    g = mlmq.Graph.from_csr(csr)
+    with pytest.raises(mlmq.MlmqError) as ei:
+        mlmq.sssp(g, 64)
+    assert ei.value.code == mlmq.ERR_INVALID_ARG
+    with pytest.raises(mlmq.MlmqError):
+        mlmq.sssp(g, 0, config=mlmq.default_config(l1_cap=100))
+    with pytest.raises(mlmq.MlmqError):
+        mlmq.sssp(g, 0, config=mlmq.default_config(l2_type=1, bmax=3))
+    with pytest.raises(mlmq.MlmqError):
+        mlmq.Graph(3, np.array([0, 1, 1, 2]), np.array([1, 5]), np.array([1, 1]))
+
+
+def test_batch_matches_alone(dev_graphs, oracle_dist):
+    mlmq = _mlmq()
+    names = ["grid64", "road96x80", "rmat12", "uniform", "path", "star", "multi"] * 3
+    gs = [dev_graphs[k][0] for k in names]
+    rng = np.random.default_rng(11)
+    srcs = [int(rng.integers(0, dev_graphs[k][1].n)) for k in names]
+    _say(f"[batch] {len(names)} queries")
+    outs, status = mlmq.sssp_batch(gs, srcs)
+    torch.cuda.synchronize()
+    assert status == [0] * len(names)
+    for k, s, o in zip(names, srcs, outs):
+        assert np.array_equal(mlmq.to_numpy(o), oracle.dijkstra(dev_graphs[k][1], s)), (k, s)
+    # a second launch reuses the captured graph
+    outs2, status2 = mlmq.sssp_batch(gs, srcs)
+    torch.cuda.synchronize()
+    assert status2 == [0] * len(names)
+    for o1, o2 in zip(outs, outs2):
+        assert torch.equal(o1, o2)
