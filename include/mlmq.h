@@ -61,6 +61,7 @@ typedef struct mlmq_stats {
   uint32_t struct_size;
   uint32_t status;         /* device status word of the last solve */
   double kernel_ms;        /* device time of init + persistent kernel (HIP events) */
+  double worker_ms;        /* device time of the persistent kernel alone */
   uint64_t expansions;     /* work items that passed the stale check */
   uint64_t stale;          /* work items dropped as stale */
   uint64_t edges;          /* edges scanned */
@@ -173,11 +174,21 @@ int mlmq_sssp_batch(const mlmq_graph* const* graphs, const uint32_t* sources, ui
 int mlmq_autotune(mlmq_graph* g, uint32_t budget_ms, mlmq_config* out);
 
 /*
- * Continuous-batching server over resident graphs: a resident persistent
- * kernel picks up queries from a slot table while others run. Queries are
- * admitted in arrival order when a slot and mem_budget_bytes of per-query
- * state (distances + queues) are free. submit never blocks (MLMQ_ERR_BUSY if
- * the pending list is full); dist_out is device memory of graphs[graph_id]'s n.
+ * Continuous-batching server over resident graphs (the serving form of the
+ * Section 4.1 persistent kernel): a resident kernel picks up queries from a
+ * table of max_slots (1..64) slots while others run; its idle waves sleep and
+ * leave after a stretch without work, and the library relaunches it when work
+ * arrives. Queries are admitted in arrival order when a slot is free and their
+ * state (queues + n distances) fits in mem_budget_bytes; a query larger than
+ * the budget runs alone. Each graph uses cfg if given, else its own config
+ * (mlmq_graph_config); graphs must outlive the server. submit never blocks
+ * (MLMQ_ERR_BUSY if 2^20 queries are pending); dist_out is device memory of
+ * graphs[graph_id]'s n uint32 that the caller keeps valid until the query
+ * finished. Each result is identical to mlmq_sssp of the same query alone.
+ * The library's streams are non-blocking; hipDeviceSynchronize waits for the
+ * resident kernel, so callers use stream or event synchronisation while a
+ * server is alive. destroy cancels pending queries, waits for running ones
+ * and stops the kernel.
  */
 int mlmq_server_create(const mlmq_graph* const* graphs, int32_t ngraphs, uint64_t mem_budget_bytes,
                        int32_t max_slots, const mlmq_config* cfg, mlmq_server** out);

@@ -50,6 +50,7 @@ class MlmqError(RuntimeError):
 class Stats(ctypes.Structure):
     _fields_ = [
         ("struct_size", ctypes.c_uint32), ("status", ctypes.c_uint32), ("kernel_ms", ctypes.c_double),
+        ("worker_ms", ctypes.c_double),
         ("expansions", ctypes.c_uint64), ("stale", ctypes.c_uint64), ("edges", ctypes.c_uint64),
         ("pushes", ctypes.c_uint64), ("l1_writes", ctypes.c_uint64), ("l1_reads", ctypes.c_uint64),
         ("l2_writes", ctypes.c_uint64), ("l2_reads", ctypes.c_uint64), ("hub_chunks", ctypes.c_uint64),

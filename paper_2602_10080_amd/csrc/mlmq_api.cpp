@@ -531,13 +531,14 @@ int status_to_code(uint32_t st) {
   }
 }
 
-void fill_stats(mlmq_stats* st, const QueryCtrl& h, double ms, uint32_t grid, uint32_t retries) {
+void fill_stats(mlmq_stats* st, const QueryCtrl& h, double ms, double worker_ms, uint32_t grid, uint32_t retries) {
   if (!st) return;
   const uint32_t sz = st->struct_size;
   std::memset(st, 0, sizeof(*st));
   st->struct_size = sz;
   st->status = h.error.v;
   st->kernel_ms = ms;
+  st->worker_ms = worker_ms;
   st->expansions = h.stats[kCtExpansions];
   st->stale = h.stats[kCtStale];
   st->edges = h.stats[kCtEdges];
@@ -682,15 +683,17 @@ int run_single(const mlmq_graph* g, uint32_t source, uint32_t* dist_out, const m
     *h_desc = make_desc(g, c, p, base, d_dist, source, shape.grid);
     uint32_t* d_beats = reinterpret_cast<uint32_t*>(base + beats_off);
     LaunchArgs a = make_args(d_desc, d_batch, 1, shape, c.timeout_ms, d_beats);
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t ev0 = nullptr, evw = nullptr, ev1 = nullptr;
     hipError_t e = hipSuccess;
     if (c.stats_out) {
       e = hipEventCreate(&ev0);
+      if (e == hipSuccess) e = hipEventCreate(&evw);
       if (e == hipSuccess) e = hipEventCreate(&ev1);
     }
     if (e == hipSuccess) e = hipMemcpyAsync(d_desc, h_desc, sizeof(QueryDesc), hipMemcpyHostToDevice, stream);
     if (e == hipSuccess && ev0) e = hipEventRecord(ev0, stream);
     if (e == hipSuccess) e = launch_init(d_desc, d_batch, 1, p.init_words, stream);
+    if (e == hipSuccess && evw) e = hipEventRecord(evw, stream);
     if (e == hipSuccess) e = launch_worker(a, shape.grid, shape.wg, shape.lds, stream);
     if (e == hipSuccess && ev1) e = hipEventRecord(ev1, stream);
     if (e == hipSuccess)
@@ -708,10 +711,12 @@ int run_single(const mlmq_graph* g, uint32_t source, uint32_t* dist_out, const m
       if (hipStreamQuery(stream) == hipSuccess) slab_release(slab);
       return set_error(MLMQ_ERR_TIMEOUT, "device overran its timeout (%s)", snap.c_str());
     }
-    float ms = 0;
+    float ms = 0, wms = 0;
     if (e == hipSuccess && ev0) e = hipEventElapsedTime(&ms, ev0, ev1);
-    if (ev0) hipEventDestroy(ev0);
-    if (ev1) hipEventDestroy(ev1);
+    if (e == hipSuccess && evw) e = hipEventElapsedTime(&wms, evw, ev1);
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (evw) (void)hipEventDestroy(evw);
+    if (ev1) (void)hipEventDestroy(ev1);
     if (e != hipSuccess) {
       slab_release(slab);
       return hip_fail(e, "solve");
@@ -747,7 +752,7 @@ int run_single(const mlmq_graph* g, uint32_t source, uint32_t* dist_out, const m
       if (e == hipSuccess) e = hipStreamSynchronize(stream);
       if (e != hipSuccess) rc = hip_fail(e, "copying distances");
     }
-    fill_stats(c.stats_out, *h_ctrl, ms, shape.grid, retries);
+    fill_stats(c.stats_out, *h_ctrl, ms, wms, shape.grid, retries);
     slab_release(slab);
     return rc;
   }

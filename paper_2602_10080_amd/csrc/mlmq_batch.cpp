@@ -171,7 +171,7 @@ extern "C" int mlmq_sssp_batch(const mlmq_graph* const* graphs, const uint32_t* 
       std::memset(&tmp, 0, sizeof(tmp));
       tmp.error.v = h_res[k].error;
       for (int j = 0; j < kNumCounters; ++j) tmp.stats[j] = h_res[k].stats[j];
-      fill_stats(cfgs[i]->stats_out, tmp, 0.0, h_desc[k].want_wgs, 0);
+      fill_stats(cfgs[i]->stats_out, tmp, 0.0, 0.0, h_desc[k].want_wgs, 0);
     }
   }
   slab_release(slab);

@@ -115,6 +115,24 @@ struct LaunchArgs {
   uint32_t* beats;          // [grid] last program point of each wave (nullable)
 };
 
+// Control words of a resident server kernel (device memory).
+struct ServerCtrl {
+  Word stop;    // 1: idle waves leave the kernel
+  Word cancel;  // 1: every query stops (status canceled)
+};
+
+struct ServerArgs {
+  const QueryDesc* slots;  // [nslots] descriptors, rewritten on admission
+  uint64_t* join;          // [nslots] slot words (see the server kernel)
+  uint64_t* done_host;     // [nslots] host-coherent: (status << 32) | generation
+  ServerCtrl* ctl;
+  int32_t nslots;          // <= 64
+  uint32_t l1_cap;         // LDS ring capacity the launch was sized for
+  uint64_t timeout_ticks;  // per-query device watchdog from the moment a wave joins
+  uint64_t cap_wait_ticks;
+  uint64_t idle_exit_ticks;  // a wave with no work for this long leaves the kernel
+};
+
 // Program points a wave reports in its heartbeat word (point << 24 | iteration).
 enum : uint32_t {
   kPtPick = 1,
@@ -143,5 +161,12 @@ hipError_t launch_worker(const LaunchArgs& a, uint32_t grid, uint32_t wg_size, s
 hipError_t launch_overflow_check(const QueryDesc* d_query, uint32_t* d_flag, hipStream_t s);
 hipError_t launch_gather(const QueryDesc* d_queries, int nq, QueryResult* d_out, hipStream_t s);
 hipError_t worker_occupancy(uint32_t wg_size, size_t lds, int* wgs_per_cu);
+hipError_t launch_server_worker(const ServerArgs& a, uint32_t grid, size_t lds, hipStream_t s);
+// Resets the query's memory, stores its descriptor in *d_slot, then stores
+// word into *d_join (two kernels in stream order).
+hipError_t launch_server_admit(const QueryDesc& q, QueryDesc* d_slot, uint64_t* d_join, uint64_t word,
+                               uint32_t max_words, hipStream_t s);
+hipError_t launch_server_signal(uint32_t* d_word, uint32_t v, hipStream_t s);
+hipError_t server_occupancy(size_t lds, int* wgs_per_cu);
 
 }  // namespace mlmq

@@ -744,6 +744,80 @@ __device__ __forceinline__ uint32_t pick_query(const LaunchArgs& a) {
   return lane_val(q, 0);
 }
 
+// ------------------------------------------------------------ kernels
+
+// Fresh wave state for query q: empty L0 and L1 (the LDS rings need no
+// clearing, only their counters), no pending tickets, no counters.
+__device__ __forceinline__ void setup_ctx(Ctx& c, const QueryDesc& q, uint64_t* smem, uint32_t l1_cap_alloc,
+                                          const uint32_t* cancel, uint64_t deadline, uint64_t cap_wait,
+                                          uint32_t* beat_word) {
+  c.q = q;
+  c.stg = smem;
+  c.l1 = smem + 64;
+  c.far = c.l1 + l1_cap_alloc;
+  c.l1mask = c.q.l1_cap - 1u;
+  c.qh = c.qt = c.fh = c.ft = 0;
+  c.thresh = c.q.l1_type == MLMQ_L1_FILTER ? c.q.delta1 : 0u;
+  c.wcount = 0;
+  c.done_acc = 0;
+  c.pend = kInf;
+  c.cancel = cancel;
+  c.deadline = deadline;
+  c.cap_wait = cap_wait;
+  c.r0 = c.r1 = c.r2 = c.r3 = 0;
+  c.l0h = c.l0n = 0;
+  c.beat = beat_word;
+  c.it = 0;
+  c.stop = false;
+  c.ovf = false;
+#pragma unroll
+  for (int i = 0; i < kNumCounters; ++i) c.ct[i] = 0;
+}
+
+// Adds this wave's counters and overflow flag to the query's control block.
+__device__ __forceinline__ void flush_counters(const Ctx& c) {
+  if (lane() == 0) {
+    QueryCtrl* ctl = c.q.ctrl;
+#pragma unroll
+    for (int i = 0; i < kNumCounters; ++i)
+      if (c.ct[i]) __hip_atomic_fetch_add(&ctl->stats[i], (uint64_t)c.ct[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (c.ovf) st32(&ctl->overflow.v, 1u);
+  }
+}
+
+// ---------------------------------------------------------------- server slots
+//
+// A server slot word packs (generation << 32) | closed << 31 | want << 16 |
+// joined. The host opens a slot (closed = 0, joined = 0) once the query's
+// memory is initialised; waves join by CAS while joined < want; the first
+// wave to leave closes it, so the set of waves on the query is final from
+// then on, and the last of them to leave reports completion to the host.
+
+constexpr uint64_t kSlotClosed = 1ull << 31;
+__device__ __forceinline__ uint32_t slot_gen(uint64_t w) { return (uint32_t)(w >> 32); }
+__device__ __forceinline__ uint32_t slot_want(uint64_t w) { return (uint32_t)(w >> 16) & 0x7FFFu; }
+__device__ __forceinline__ uint32_t slot_joined(uint64_t w) { return (uint32_t)w & 0xFFFFu; }
+__device__ __forceinline__ bool slot_open(uint64_t w) {
+  return slot_gen(w) != 0 && (w & kSlotClosed) == 0 && slot_joined(w) < slot_want(w);
+}
+
+// Loads a descriptor with coherent loads (lane i reads 8-byte word i): the
+// slot table is rewritten while the kernel runs, so no cached copy may be used.
+__device__ __forceinline__ QueryDesc load_desc_coherent(const QueryDesc* d) {
+  static_assert(sizeof(QueryDesc) % 8 == 0 && sizeof(QueryDesc) / 8 <= 64, "descriptor layout");
+  constexpr int kWords = sizeof(QueryDesc) / 8;
+  const uint64_t mine = lane() < (uint32_t)kWords ? ld64(reinterpret_cast<const uint64_t*>(d) + lane()) : 0ull;
+  uint64_t w[kWords];
+#pragma unroll
+  for (int i = 0; i < kWords; ++i) {
+    const uint32_t lo = lane_val((uint32_t)mine, (uint32_t)i), hi = lane_val((uint32_t)(mine >> 32), (uint32_t)i);
+    w[i] = (uint64_t)lo | ((uint64_t)hi << 32);
+  }
+  QueryDesc q;
+  __builtin_memcpy(&q, w, sizeof(q));
+  return q;
+}
+
 }  // namespace
 
 // ------------------------------------------------------------ kernels
@@ -758,35 +832,72 @@ __global__ void __launch_bounds__(64) mlmq_worker(LaunchArgs a) {
     const uint32_t qi = pick_query(a);
     if (qi == kInf) break;
     Ctx c;
-    c.q = a.queries[qi];
-    c.stg = smem;
-    c.l1 = smem + 64;
-    c.far = c.l1 + a.l1_cap;
-    c.l1mask = c.q.l1_cap - 1u;
-    c.qh = c.qt = c.fh = c.ft = 0;
-    c.thresh = c.q.l1_type == MLMQ_L1_FILTER ? c.q.delta1 : 0u;
-    c.wcount = 0;
-    c.done_acc = 0;
-    c.pend = kInf;
-    c.cancel = &a.batch->cancel.v;
-    c.deadline = t0 + a.timeout_ticks;
-    c.cap_wait = a.cap_wait_ticks;
-    c.r0 = c.r1 = c.r2 = c.r3 = 0;
-    c.l0h = c.l0n = 0;
-    c.beat = my_beat;
-    c.it = 0;
-    c.stop = false;
-    c.ovf = false;
-#pragma unroll
-    for (int i = 0; i < kNumCounters; ++i) c.ct[i] = 0;
+    setup_ctx(c, a.queries[qi], smem, a.l1_cap, &a.batch->cancel.v, t0 + a.timeout_ticks, a.cap_wait_ticks, my_beat);
     run_query(c);
-    if (lane() == 0) {
-      QueryCtrl* ctl = c.q.ctrl;
-#pragma unroll
-      for (int i = 0; i < kNumCounters; ++i)
-        if (c.ct[i]) __hip_atomic_fetch_add(&ctl->stats[i], (uint64_t)c.ct[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (c.ovf) st32(&ctl->overflow.v, 1u);
-      add32(&ctl->finished.v, 1u);
+    flush_counters(c);
+    if (lane() == 0) add32(&c.q.ctrl->finished.v, 1u);
+  }
+}
+
+// Resident server kernel: each wave repeatedly joins the oldest open slot,
+// works on that query until it terminates, and leaves. Idle waves sleep and
+// leave the kernel on the host's stop flag or after idle_exit_ticks without
+// work (the host relaunches the kernel when work arrives and none is left).
+__global__ void __launch_bounds__(64) mlmq_server_worker(ServerArgs a) {
+  extern __shared__ uint64_t smem[];
+  uint64_t last_busy = (uint64_t)wall_clock64();
+  uint32_t idle = 0;
+  for (;;) {
+    const uint32_t l = lane();
+    const uint64_t w = l < (uint32_t)a.nslots ? ld64(&a.join[l]) : 0ull;
+    const bool open = slot_open(w);
+    const uint32_t g = uni(wave_min(open ? slot_gen(w) : kInf));
+    if (g != kInf) {
+      const uint32_t s = first_lane(ballot(open && slot_gen(w) == g));
+      const uint64_t ws = uni64(__builtin_amdgcn_readlane((uint32_t)w, s) |
+                                ((uint64_t)__builtin_amdgcn_readlane((uint32_t)(w >> 32), s) << 32));
+      uint32_t won = 0;
+      if (l == 0) {
+        uint64_t expect = ws;
+        won = __hip_atomic_compare_exchange_strong(&a.join[s], &expect, ws + 1u, __ATOMIC_ACQ_REL,
+                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                  ? 1u
+                  : 0u;
+      }
+      if (!lane_val(won, 0)) continue;
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      const QueryDesc q = load_desc_coherent(a.slots + s);
+      Ctx c;
+      setup_ctx(c, q, smem, a.l1_cap, &a.ctl->cancel.v, (uint64_t)wall_clock64() + a.timeout_ticks, a.cap_wait_ticks,
+                nullptr);
+      run_query(c);
+      flush_counters(c);
+      if (l == 0) {
+        const uint64_t before = __hip_atomic_fetch_or(&a.join[s], kSlotClosed, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t left = __hip_atomic_fetch_add(&c.q.ctrl->finished.v, 1u, __ATOMIC_ACQ_REL,
+                                                     __HIP_MEMORY_SCOPE_AGENT) + 1u;
+        if (left == slot_joined(before)) {
+          // last wave out: every other wave's updates happened before its
+          // finished increment; publish status and generation to the host
+          const uint32_t err = ld32(&c.q.ctrl->error.v);
+          const uint32_t ovf = ld32(&c.q.ctrl->overflow.v);
+          const uint64_t word = ((uint64_t)(err | (ovf << 8)) << 32) | slot_gen(before);
+          __hip_atomic_store(&a.done_host[s], word, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+      }
+      last_busy = (uint64_t)wall_clock64();
+      idle = 0;
+      continue;
+    }
+    if (uni(ld32(&a.ctl->stop.v))) break;
+    if ((uint64_t)wall_clock64() - last_busy > a.idle_exit_ticks) break;
+    ++idle;
+    backoff(min(idle >> 2, 6u));
+    // long-idle waves poll the slot table less often (up to ~50 us apart)
+    for (uint32_t k = idle >> 6; k > 0 && k < 16; --k) __builtin_amdgcn_s_sleep(127);
+    if (idle >= 1024) {
+      for (uint32_t k = 0; k < 15; ++k) __builtin_amdgcn_s_sleep(127);
     }
   }
 }
@@ -794,14 +905,7 @@ __global__ void __launch_bounds__(64) mlmq_worker(LaunchArgs a) {
 // Per-query reset: dist = UINT32_MAX except dist[source] = 0, all L2 slots
 // free except ring 0 / slot 0, which holds the source (it is written through
 // to L2 before the worker starts, Section 4.1), counters zero, reservation 1.
-__global__ void mlmq_init(const QueryDesc* qs, BatchCtrl* batch) {
-  const QueryDesc& q = qs[blockIdx.y];
-  const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
-  const uint32_t stride = gridDim.x * blockDim.x;
-  if (blockIdx.y == 0 && tid == 0) {
-    batch->cursor.v = 0;
-    batch->cancel.v = 0;
-  }
+__device__ __forceinline__ void init_query(const QueryDesc& q, uint32_t tid, uint32_t stride) {
   const uint32_t n = q.n, src = q.source;
   uint32_t* dist = q.dist;
   for (uint32_t i = tid; i < n; i += stride) dist[i] = i == src ? 0u : kInf;
@@ -821,6 +925,35 @@ __global__ void mlmq_init(const QueryDesc* qs, BatchCtrl* batch) {
   uint32_t* cwp = reinterpret_cast<uint32_t*>(q.ctrl);
   for (uint32_t i = tid; i < cw; i += stride) cwp[i] = 0;
   if (tid == 0) q.data[0] = make_elem(src, 0);
+}
+
+__global__ void mlmq_init(const QueryDesc* qs, BatchCtrl* batch) {
+  const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (blockIdx.y == 0 && tid == 0) {
+    batch->cursor.v = 0;
+    batch->cancel.v = 0;
+  }
+  init_query(qs[blockIdx.y], tid, gridDim.x * blockDim.x);
+}
+
+// Server admission, step 1: the query's memory is reset as above and its
+// descriptor is stored into its slot.
+__global__ void mlmq_server_init(QueryDesc q, QueryDesc* slot) {
+  const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid == 0) *slot = q;
+  init_query(q, tid, gridDim.x * blockDim.x);
+}
+
+// Server admission, step 2 (a later kernel in the same stream, so every store
+// of step 1 is complete): opens the slot.
+__global__ void mlmq_server_publish(uint64_t* join, uint64_t word) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) __hip_atomic_store(join, word, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Stores one control word (stop / cancel) coherently while the resident
+// kernel runs.
+__global__ void mlmq_server_signal(uint32_t* p, uint32_t v) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Overflow test (exact): some reachable vertex has a distance >= 2^32 - 1 iff
@@ -875,6 +1008,31 @@ hipError_t launch_overflow_check(const QueryDesc* d_query, uint32_t* d_flag, hip
 hipError_t launch_gather(const QueryDesc* d_queries, int nq, QueryResult* d_out, hipStream_t s) {
   hipLaunchKernelGGL(mlmq_gather, dim3((uint32_t)(nq + 255) / 256u), dim3(256), 0, s, d_queries, nq, d_out);
   return hipGetLastError();
+}
+
+hipError_t launch_server_worker(const ServerArgs& a, uint32_t grid, size_t lds, hipStream_t s) {
+  hipLaunchKernelGGL(mlmq_server_worker, dim3(grid), dim3(64), lds, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_server_admit(const QueryDesc& q, QueryDesc* d_slot, uint64_t* d_join, uint64_t word,
+                               uint32_t max_words, hipStream_t s) {
+  uint32_t blocks = (max_words + 255u) / 256u;
+  blocks = blocks < 1u ? 1u : (blocks > 2048u ? 2048u : blocks);
+  hipLaunchKernelGGL(mlmq_server_init, dim3(blocks), dim3(256), 0, s, q, d_slot);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(mlmq_server_publish, dim3(1), dim3(64), 0, s, d_join, word);
+  return hipGetLastError();
+}
+
+hipError_t launch_server_signal(uint32_t* d_word, uint32_t v, hipStream_t s) {
+  hipLaunchKernelGGL(mlmq_server_signal, dim3(1), dim3(64), 0, s, d_word, v);
+  return hipGetLastError();
+}
+
+hipError_t server_occupancy(size_t lds, int* wgs_per_cu) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(wgs_per_cu, mlmq_server_worker, 64, lds);
 }
 
 hipError_t worker_occupancy(uint32_t wg_size, size_t lds, int* wgs_per_cu) {

@@ -192,6 +192,9 @@ inline void __hip_atomic_store(T* p, U v, int, int) { __atomic_store_n(p, (T)v, 
 template <class T, class U>
 inline T __hip_atomic_fetch_add(T* p, U v, int, int) { return __atomic_fetch_add(p, (T)v, __ATOMIC_SEQ_CST); }
 template <class T, class U>
+inline T __hip_atomic_fetch_or(T* p, U v, int, int) { return __atomic_fetch_or(p, (T)v, __ATOMIC_SEQ_CST); }
+inline void __builtin_amdgcn_fence(int, const char*) { __atomic_thread_fence(__ATOMIC_SEQ_CST); }
+template <class T, class U>
 inline T __hip_atomic_fetch_min(T* p, U v, int, int) {
   T old = __atomic_load_n(p, __ATOMIC_SEQ_CST);
   while (old > (T)v && !__atomic_compare_exchange_n(p, &old, (T)v, false, __ATOMIC_SEQ_CST, __ATOMIC_SEQ_CST)) {

@@ -89,7 +89,7 @@ def test_parity(dev_graphs, oracle_dist, graph_name, cfg_name):
     mlmq = _mlmq()
     g, csr, src = dev_graphs[graph_name]
     _say(f"[parity] graph={graph_name} n={csr.n} m={csr.m} src={src} cfg={cfg_name}")
-    cfg = mlmq.default_config(**CONFIGS[cfg_name], timeout_ms=20000)
+    cfg = mlmq.default_config(**CONFIGS[cfg_name], timeout_ms=10000)
     try:
         out, st = mlmq.sssp(g, src, config=cfg, stats=True)
     except mlmq.MlmqError as e:
