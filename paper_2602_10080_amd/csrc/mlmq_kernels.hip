@@ -570,35 +570,91 @@ __device__ __forceinline__ void emit(Ctx& c, uint32_t v, uint32_t nd, bool imp) 
 
 // ------------------------------------------------------------ relaxation
 
-// Relax one edge per lane (the relax step of the paper's kernel sketch, with
-// atomicMin): candidate nd = d + w; a plain load of dist[v] filters hopeless
-// candidates, then atomicMin decides; the lane has new work iff nd < the
-// previous label.
-__device__ __forceinline__ void relax_emit(Ctx& c, bool has, uint32_t ed, uint32_t d) {
-  uint32_t v = 0, nd = 0;
-  bool imp = false, of = false;
-  if (has) {
-    const uint64_t a = c.q.adj[ed];
-    v = (uint32_t)a;
-    const uint64_t s = (uint64_t)d + (a >> 32);
-    if (s >= kInf) {
-      of = true;
-    } else {
-      nd = (uint32_t)s;
-      if (nd < ld_label(c.q.dist + v)) {
-        const uint32_t old = __hip_atomic_fetch_min(c.q.dist + v, nd, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        imp = nd < old;
-      }
+// Edges a lane relaxes per step: the loads of all of them are issued before
+// any result is used, so a wave has kRelaxUnroll independent memory chains
+// in flight instead of one.
+constexpr int kRelaxUnroll = 4;
+
+// Relax U sub-batches of 64 edges (one edge per lane each; the relax step of
+// the paper's kernel sketch, with atomicMin): candidate nd = d + w
+// (saturating), a plain load of dist[v] filters hopeless candidates, then
+// atomicMin decides; a lane has new work iff nd < the previous label.
+// Lanes without an edge load entry 0 of adj / dist (both exist whenever
+// there is an edge to relax) so that every load is unconditional.
+template <int U>
+__device__ __forceinline__ void relax_many(Ctx& c, const bool (&has)[U], const uint32_t (&ed)[U],
+                                           const uint32_t (&d)[U]) {
+  uint64_t a[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const uint32_t eidx = has[u] ? ed[u] : 0u;
+    a[u] = c.q.adj[eidx];
+  }
+  uint32_t v[U], nd[U], lab[U];
+  bool cand[U];
+  bool of = false;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const uint64_t sum = (uint64_t)d[u] + (a[u] >> 32);
+    of = of || (has[u] && sum >= kInf);
+    cand[u] = has[u] && sum < kInf;
+    v[u] = (uint32_t)a[u];
+    nd[u] = (uint32_t)sum;
+    const uint32_t lv = cand[u] ? v[u] : 0u;
+    lab[u] = ld_label(c.q.dist + lv);
+  }
+  bool imp[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    imp[u] = false;
+    if (cand[u] && nd[u] < lab[u]) {
+      const uint32_t old =
+          __hip_atomic_fetch_min(c.q.dist + v[u], nd[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      imp[u] = nd[u] < old;
     }
   }
-  c.ct[kCtEdges] += popc(ballot(has));
+  uint32_t nedges = 0;
+#pragma unroll
+  for (int u = 0; u < U; ++u) nedges += popc(ballot(has[u]));
+  c.ct[kCtEdges] += nedges;
   if (ballot(of)) c.ovf = true;
-  emit(c, v, nd, imp);
+#pragma unroll
+  for (int u = 0; u < U; ++u) emit(c, v[u], nd[u], imp[u]);
 }
 
 // Whole wave sweeps the edge range [eb, ee) of one vertex.
 __device__ __forceinline__ void process_range(Ctx& c, uint32_t d, uint32_t eb, uint32_t ee) {
-  for (uint32_t x = eb; x < ee && !c.stop; x += 64) relax_emit(c, x + lane() < ee, x + lane(), d);
+  constexpr int U = kRelaxUnroll;
+  uint32_t x = eb;
+  for (; x + 64u * U <= ee && !c.stop; x += 64u * U) {
+    bool has[U];
+    uint32_t ed[U], dd[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      has[u] = true;
+      ed[u] = x + 64u * u + lane();
+      dd[u] = d;
+    }
+    relax_many<U>(c, has, ed, dd);
+  }
+  for (; x < ee && !c.stop; x += 64) {
+    bool has[1] = {x + lane() < ee};
+    uint32_t ed[1] = {x + lane()}, dd[1] = {d};
+    relax_many<1>(c, has, ed, dd);
+  }
+}
+
+// Edge idx of the flattened batch: lane j owns edges [excl_j, incl_j) of the
+// batch, starting at CSR position beg_j; binary search over the inclusive scan.
+__device__ __forceinline__ void flat_edge(uint32_t idx, uint32_t incl, uint32_t excl, uint32_t beg, uint32_t d,
+                                          uint32_t& ed, uint32_t& dd) {
+  uint32_t j = 0;
+#pragma unroll
+  for (uint32_t st = 32; st; st >>= 1) {
+    if ((uint32_t)__shfl(incl, (int)(j + st - 1)) <= idx) j += st;
+  }
+  ed = (uint32_t)__shfl(beg, (int)j) + (idx - (uint32_t)__shfl(excl, (int)j));
+  dd = (uint32_t)__shfl(d, (int)j);
 }
 
 // Relaxation of a batch (the paper's SSSP_relax with the load balancing of
@@ -607,15 +663,16 @@ __device__ __forceinline__ void process_range(Ctx& c, uint32_t d, uint32_t eb, u
 // edges of the remaining vertices evenly over the lanes.
 __device__ __forceinline__ void process_vec(Ctx& c, uint64_t e, bool ok) {
   const uint32_t v = elem_v(e), d = elem_d(e);
-  const bool stale = ok && d > ld_label(c.q.dist + v);
+  // label and row bounds are loaded together (vertex 0 for idle lanes)
+  const uint32_t lv = ok ? v : 0u;
+  const uint32_t label = ld_label(c.q.dist + lv);
+  const uint32_t beg0 = (uint32_t)c.q.off[lv];
+  const uint32_t end0 = (uint32_t)c.q.off[lv + 1];
+  const bool stale = ok && d > label;
   c.ct[kCtStale] += popc(ballot(stale));
   ok = ok && !stale;
   c.ct[kCtExpansions] += popc(ballot(ok));
-  uint32_t beg = 0, end = 0;
-  if (ok) {
-    beg = (uint32_t)c.q.off[v];
-    end = (uint32_t)c.q.off[v + 1];
-  }
+  const uint32_t beg = ok ? beg0 : 0u, end = ok ? end0 : 0u;
   const uint32_t deg = end - beg;
   if (c.q.th_hub) {
     const bool hub = ok && deg > c.q.th_hub;
@@ -630,15 +687,25 @@ __device__ __forceinline__ void process_vec(Ctx& c, uint64_t e, bool ok) {
   const uint32_t incl = wave_incl_scan(sdeg);
   const uint32_t total = lane_val(incl, 63);
   const uint32_t excl = incl - sdeg;
-  for (uint32_t base = 0; base < total && !c.stop; base += 64) {
-    const uint32_t idx = base + lane();
-    uint32_t j = 0;
+  constexpr int U = kRelaxUnroll;
+  uint32_t base = 0;
+  for (; base + 64u * (U - 1) < total && !c.stop; base += 64u * U) {
+    bool has[U];
+    uint32_t ed[U], dd[U];
 #pragma unroll
-    for (uint32_t st = 32; st; st >>= 1) {
-      if ((uint32_t)__shfl(incl, (int)(j + st - 1)) <= idx) j += st;
+    for (int u = 0; u < U; ++u) {
+      const uint32_t idx = base + 64u * u + lane();
+      has[u] = idx < total;
+      flat_edge(has[u] ? idx : 0u, incl, excl, beg, d, ed[u], dd[u]);
     }
-    const uint32_t ed = (uint32_t)__shfl(beg, (int)j) + (idx - (uint32_t)__shfl(excl, (int)j));
-    relax_emit(c, idx < total, ed, (uint32_t)__shfl(d, (int)j));
+    relax_many<U>(c, has, ed, dd);
+  }
+  for (; base < total && !c.stop; base += 64) {
+    const uint32_t idx = base + lane();
+    bool has[1] = {idx < total};
+    uint32_t ed[1], dd[1];
+    flat_edge(has[0] ? idx : 0u, incl, excl, beg, d, ed[0], dd[0]);
+    relax_many<1>(c, has, ed, dd);
   }
   uint64_t mb = ballot(big);
   while (mb && !c.stop) {

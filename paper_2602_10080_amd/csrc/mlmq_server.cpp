@@ -131,6 +131,10 @@ struct mlmq_server {
   std::vector<Slot> slots;
   uint32_t next_gen = 1;
   uint32_t launches = 0;
+  uint32_t timeout_ms = 60000;
+  uint64_t quit_ns = 0;
+  bool cancel_sent = false;
+  bool leak = false;  // the device never let go of the server's memory
 };
 
 namespace {
@@ -303,6 +307,20 @@ void server_loop(mlmq_server* s) {
       bool busy = false;
       for (const Slot& sl : s->slots) busy |= sl.phase != Phase::kFree;
       if (!busy) return;
+      // running queries end at their device deadline; past it (plus slack),
+      // cancel them, and if even that is not answered, give up on the memory
+      const uint64_t now = now_ns();
+      if (!s->quit_ns) s->quit_ns = now;
+      const uint64_t grace = (uint64_t)(s->timeout_ms + 5000) * 1000000ull;
+      if (!s->cancel_sent && now - s->quit_ns > grace) {
+        s->cancel_sent = true;
+        (void)launch_server_signal(&s->d_ctl->cancel.v, 1u, s->cs);
+      }
+      if (now - s->quit_ns > grace + 5000000000ull) {
+        s->leak = true;
+        fail_all(s, MLMQ_ERR_TIMEOUT);
+        return;
+      }
     }
     if (!any) s->cv_work.wait_for(lk, std::chrono::microseconds(20));
   }
@@ -402,7 +420,8 @@ int mlmq_server_create(const mlmq_graph* const* graphs, int32_t ngraphs, uint64_
   a.ctl = s->d_ctl;
   a.nslots = max_slots;
   a.l1_cap = l1_alloc;
-  a.timeout_ticks = (uint64_t)(timeout_ms ? timeout_ms : 60000) * di->ticks_per_ms;
+  s->timeout_ms = timeout_ms ? timeout_ms : 60000;
+  a.timeout_ticks = (uint64_t)s->timeout_ms * di->ticks_per_ms;
   a.cap_wait_ticks = 20ull * di->ticks_per_ms;
   a.idle_exit_ticks = 200ull * di->ticks_per_ms;
   s->th = std::thread(server_loop, s);
@@ -480,11 +499,20 @@ void mlmq_server_destroy(mlmq_server* s) {
       const auto limit = clk::now() + std::chrono::milliseconds(5000);
       while (hipStreamQuery(s->ws) == hipErrorNotReady && clk::now() < limit)
         std::this_thread::sleep_for(std::chrono::microseconds(200));
-      if (hipStreamQuery(s->ws) == hipErrorNotReady) (void)launch_server_signal(&s->d_ctl->cancel.v, 1u, s->cs);
+      if (hipStreamQuery(s->ws) == hipErrorNotReady) {
+        (void)launch_server_signal(&s->d_ctl->cancel.v, 1u, s->cs);
+        const auto limit2 = clk::now() + std::chrono::milliseconds(5000);
+        while (hipStreamQuery(s->ws) == hipErrorNotReady && clk::now() < limit2)
+          std::this_thread::sleep_for(std::chrono::microseconds(200));
+      }
     }
-    (void)hipStreamSynchronize(s->ws);
   }
   if (s->cs) (void)hipStreamSynchronize(s->cs);
+  if (s->leak || (s->ws && hipStreamQuery(s->ws) != hipSuccess)) {
+    // a kernel may still touch this memory: keep it for the process lifetime
+    delete s;
+    return;
+  }
   for (Slot& sl : s->slots)
     if (sl.ev) (void)hipEventDestroy(sl.ev);
   if (s->ws) (void)hipStreamDestroy(s->ws);

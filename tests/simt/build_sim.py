@@ -19,10 +19,13 @@ def transformed_source(checked: bool = False) -> str:
     src = open(KERNEL).read()
     if checked:
         # bounds-check every edge and vertex index the kernel dereferences
-        src = src.replace("c.q.adj[ed]", "c.q.adj[simt_chk(ed, (uint64_t)c.q.off[c.q.n], \"adj\", __LINE__)]")
-        src = src.replace("c.q.off[v]", "c.q.off[simt_chk(v, c.q.n, \"off\", __LINE__)]")
-        src = src.replace("c.q.dist + v", "c.q.dist + simt_chk(v, c.q.n, \"dist\", __LINE__)")
+        src = src.replace("c.q.adj[eidx]", "c.q.adj[simt_chk(eidx, (uint64_t)c.q.off[c.q.n], \"adj\", __LINE__)]")
+        src = src.replace("c.q.off[lv]", "c.q.off[simt_chk(lv, c.q.n, \"off\", __LINE__)]")
+        src = src.replace("c.q.dist + lv", "c.q.dist + simt_chk(lv, c.q.n, \"dist\", __LINE__)")
+        src = src.replace("c.q.dist + v[u]", "c.q.dist + simt_chk(v[u], c.q.n, \"dist\", __LINE__)")
         src = src.replace("c.q.dist + hv", "c.q.dist + simt_chk(hv, c.q.n, \"dist\", __LINE__)")
+        for pat in ("c.q.adj[eidx]", "c.q.off[lv]", "c.q.dist + lv", "c.q.dist + v[u]", "c.q.dist + hv"):
+            assert pat in open(KERNEL).read(), pat
     src = src.replace("extern __shared__ uint64_t smem[];",
                       "uint64_t* smem = reinterpret_cast<uint64_t*>(simt::group->lds);")
     src = re.sub(r'asm volatile\("([^"]*)"\s*:::\s*"memory"\);', lambda mo: 'simt::wave_sync_at("asm ' + mo.group(1) + '");', src)

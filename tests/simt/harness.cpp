@@ -1,5 +1,7 @@
 // Runs the library's init and persistent worker kernels on the CPU (one host
 // thread per lane) for small graphs. Test infrastructure only.
+#include <atomic>
+#include <chrono>
 #include <cstdio>
 #include <cstdlib>
 #include <vector>
@@ -163,4 +165,159 @@ extern "C" int sim_sssp(int32_t n, const int32_t* off, const int32_t* col, const
   free(batch);
   free(q);
   return 0;
+}
+
+// Serving form: nq queries (sources srcs[i], outputs dist + i * n) through the
+// resident server kernel with nslots slots and nwg one-wave workgroups. A host
+// driver thread plays the library's admission loop: it resets a query's memory
+// (init kernel, run serially), opens its slot (publish kernel), watches the
+// completion words, and admits the next query in arrival order.
+extern "C" int sim_server(int32_t n, const int32_t* off, const int32_t* col, const uint32_t* w, int32_t nq,
+                          const uint32_t* srcs, uint32_t* dist, const uint32_t* k, uint32_t nwg, int32_t nslots,
+                          uint32_t want, uint32_t* status) {
+  const int64_t m = off[n];
+  std::vector<uint64_t> adj((size_t)m + 1);
+  for (int64_t e = 0; e < m; ++e) adj[e] = (uint32_t)col[e] | ((uint64_t)w[e] << 32);
+  const uint32_t nrings = k[2] == 1 ? k[7] : 1;
+  const uint32_t nb_log2 = k[12], hub_cap = k[13];
+  const uint64_t nh = (uint64_t)nrings << nb_log2;
+  QueryDesc* slots = zalloc<QueryDesc>(64);
+  uint64_t* join = zalloc<uint64_t>(64);
+  uint64_t* done = zalloc<uint64_t>(64);
+  ServerCtrl* ctl = zalloc<ServerCtrl>(1);
+  for (int i = 0; i < 64; ++i) {
+    join[i] = 1ull << 31;  // closed
+    done[i] = 0;
+  }
+  ctl->stop.v = 0;
+  ctl->cancel.v = 0;
+  const uint32_t l1cap = k[1] == MLMQ_L1_NONE ? 64u : k[3];
+  const bool two = k[1] == MLMQ_L1_NEARFAR;
+  const size_t lds = worker_lds_bytes(1, l1cap, two);
+  ServerArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.slots = slots;
+  a.join = join;
+  a.done_host = done;
+  a.ctl = ctl;
+  a.nslots = nslots;
+  a.l1_cap = l1cap;
+  a.timeout_ticks = (uint64_t)k[14] * 100000ull;
+  a.cap_wait_ticks = 200ull * 100000ull;
+  a.idle_exit_ticks = (uint64_t)k[14] * 100000ull;
+
+  std::vector<simt::Wave*> wv;
+  std::vector<simt::Group> grp(nwg);
+  std::vector<std::barrier<>*> bars;
+  std::vector<uint8_t*> ldsb;
+  for (uint32_t g = 0; g < nwg; ++g) {
+    bars.push_back(new std::barrier<>(64));
+    ldsb.push_back(zalloc<uint8_t>(lds));
+    grp[g].bar = bars.back();
+    grp[g].lds = ldsb.back();
+    wv.push_back(new simt::Wave());
+  }
+  std::vector<std::thread> th;
+  for (uint32_t g = 0; g < nwg; ++g)
+    for (uint32_t t = 0; t < 64; ++t)
+      th.emplace_back([&, g, t] {
+        simt::lane = t;
+        simt::nops = 0;
+        simt::wave = wv[g];
+        simt::group = &grp[g];
+        simt::tidx = dim3(t);
+        simt::bidx = dim3(g);
+        simt::bdim = dim3(64);
+        simt::gdim = dim3(nwg);
+        mlmq_server_worker(a);
+      });
+
+  struct Mem {
+    QueryCtrl* ctrl;
+    RingCtr* rings;
+    uint64_t *hdr, *data, *hub_rec;
+    uint32_t *hub_cur, *hub_pub;
+  };
+  std::vector<int32_t> slot_q(nslots, -1);
+  std::vector<uint32_t> slot_gen(nslots, 0);
+  std::vector<Mem> slot_mem(nslots);
+  int32_t next = 0, finished = 0;
+  uint32_t gen = 1;
+  const auto t_end = std::chrono::steady_clock::now() + std::chrono::milliseconds(k[14] + 5000);
+  while (finished < nq && std::chrono::steady_clock::now() < t_end) {
+    for (int32_t s = 0; s < nslots; ++s) {
+      if (slot_q[s] >= 0) {
+        const uint64_t wd = __atomic_load_n(&done[s], __ATOMIC_ACQUIRE);
+        if ((uint32_t)wd != slot_gen[s]) continue;
+        status[slot_q[s]] = (uint32_t)(wd >> 32);
+        Mem& mm = slot_mem[s];
+        free(mm.ctrl), free(mm.rings), free(mm.hdr), free(mm.data), free(mm.hub_rec), free(mm.hub_cur),
+            free(mm.hub_pub);
+        slot_q[s] = -1;
+        ++finished;
+      }
+      if (slot_q[s] < 0 && next < nq) {
+        const int32_t qi = next++;
+        Mem mm{zalloc<QueryCtrl>(1), zalloc<RingCtr>(nrings), zalloc<uint64_t>(nh), zalloc<uint64_t>(nh * 64),
+               zalloc<uint64_t>(2ull * hub_cap), zalloc<uint32_t>(hub_cap), zalloc<uint32_t>(hub_cap)};
+        QueryDesc q;
+        std::memset(&q, 0, sizeof(q));
+        q.off = off;
+        q.adj = adj.data();
+        q.dist = dist + (size_t)qi * n;
+        q.ctrl = mm.ctrl;
+        q.rings = mm.rings;
+        q.hdr = mm.hdr;
+        q.data = mm.data;
+        q.hub_rec = mm.hub_rec;
+        q.hub_cur = mm.hub_cur;
+        q.hub_pub = mm.hub_pub;
+        q.n = (uint32_t)n;
+        q.source = srcs[qi];
+        q.nb_log2 = nb_log2;
+        q.nrings = nrings;
+        q.hub_cap = hub_cap;
+        q.l0_cap = 64u * k[0];
+        q.l1_type = k[1];
+        q.l2_type = k[2];
+        q.l1_cap = l1cap;
+        q.l1_wb = k[4];
+        q.delta1 = k[5];
+        q.d2_log2 = k[6];
+        q.bnum = k[2] == 1 ? k[8] : 1;
+        q.th_v = k[9];
+        q.th_hub = k[10];
+        q.hub_chunk = k[11];
+        q.want_wgs = want;
+        __atomic_store_n(&done[s], 0ull, __ATOMIC_RELEASE);
+        simt::gdim = dim3(4, 1);
+        simt::bdim = dim3(256);
+        for (uint32_t b = 0; b < 4; ++b)
+          for (uint32_t t = 0; t < 256; ++t) {
+            simt::bidx = dim3(b, 0);
+            simt::tidx = dim3(t);
+            mlmq_server_init(q, slots + s);
+          }
+        simt::gdim = dim3(1);
+        simt::bdim = dim3(64);
+        simt::bidx = dim3(0);
+        simt::tidx = dim3(0);
+        mlmq_server_publish(join + s, ((uint64_t)gen << 32) | ((uint64_t)want << 16));
+        slot_q[s] = qi;
+        slot_gen[s] = gen++;
+        slot_mem[s] = mm;
+      }
+    }
+    std::this_thread::yield();
+  }
+  __atomic_store_n(&ctl->stop.v, 1u, __ATOMIC_SEQ_CST);
+  for (auto& t : th) t.join();
+  for (auto* p : wv) delete p;
+  for (auto* p : bars) delete p;
+  for (auto* p : ldsb) free(p);
+  free(slots);
+  free(join);
+  free(done);
+  free(ctl);
+  return finished == nq ? 0 : -1;
 }

@@ -70,3 +70,30 @@ def test_kernel_on_cpu_matches_oracle(sim, graph, cfg):
     assert np.array_equal(dist, oracle.dijkstra(csr, src))
     # delayed counting balanced: every reserved block was consumed
     assert status[2] >= 1
+
+
+@pytest.mark.parametrize("cfg", ["L0x2-L1V-L2V", "L1FQ-L2DQ-hub"])
+@pytest.mark.parametrize("nslots,want", [(2, 3), (3, 8)])
+def test_server_kernel_on_cpu_matches_oracle(sim, cfg, nslots, want):
+    """Slot protocol of the resident server kernel: queries join, run next to
+    each other, close, and the last wave out reports completion; each result
+    equals the oracle's. 6 waves, so queries share the grid when want < 6."""
+    csr, _ = GRAPHS["road24"]()
+    srcs = np.array([0, 77, 479, 200, 13, 77, 301], np.uint32)
+    nq = len(srcs)
+    off = csr.off32()
+    col = np.ascontiguousarray(csr.col, np.int32)
+    w = np.ascontiguousarray(csr.w, np.uint32)
+    dist = np.zeros((nq, csr.n), np.uint32)
+    status = np.full(nq, 0xFFFF, np.uint32)
+    k = np.array(CFG[cfg], np.uint32)
+    vp = ctypes.c_void_p
+    sim.sim_server.restype = ctypes.c_int
+    rc = sim.sim_server(ctypes.c_int32(csr.n), vp(off.ctypes.data), vp(col.ctypes.data), vp(w.ctypes.data),
+                        ctypes.c_int32(nq), vp(srcs.ctypes.data), vp(dist.ctypes.data), vp(k.ctypes.data),
+                        ctypes.c_uint32(6), ctypes.c_int32(nslots), ctypes.c_uint32(want),
+                        vp(status.ctypes.data))
+    assert rc == 0, "not every query completed"
+    assert (status == 0).all(), status
+    for i, s in enumerate(srcs):
+        assert np.array_equal(dist[i], oracle.dijkstra(csr, int(s))), i
