@@ -117,6 +117,138 @@ def cpu_baseline(csr, src, gpu_dist, max_seconds=30.0):
                 seconds=t), bool(np.array_equal(want, gpu_dist))
 
 
+def bench_batch(mlmq, torch, tune_ms, nrmat=256, ngrid=64):
+    """Many queries in one persistent launch vs the same queries as sequential
+    plain solves (graphs resident, autotuned config per graph for both)."""
+    rmat = gg.rmat(20, 16, seed=1)
+    grid = gg.grid(1024, 1024, 0.05, seed=1)
+    gr, gd = mlmq.Graph.from_csr(rmat), mlmq.Graph.from_csr(grid)
+    t0 = time.perf_counter()
+    cr = mlmq.autotune(gr, tune_ms)
+    cd = mlmq.autotune(gd, tune_ms)
+    log(f"[bench] batch: autotuned in {time.perf_counter() - t0:.1f}s")
+    srcs = [int(x) for x in gg.sample_sources(rmat, nrmat, seed=2)] + \
+           [int(x) for x in gg.sample_sources(grid, ngrid, seed=3)]
+    graphs = [gr] * nrmat + [gd] * ngrid
+    cfgs = [cr] * nrmat + [cd] * ngrid
+    csrs = [rmat] * nrmat + [grid] * ngrid
+    outs = [mlmq.new_dist(c.n) for c in csrs]
+    seq = [mlmq.new_dist(c.n) for c in csrs]
+    stream = torch.cuda.current_stream()
+    mlmq.sssp_batch(graphs, srcs, outs=outs, configs=cfgs, stream=stream)  # warm-up (captures the launch)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, status = mlmq.sssp_batch(graphs, srcs, outs=outs, configs=cfgs, stream=stream)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    for g, s, o, c in zip(graphs[:4], srcs[:4], seq[:4], cfgs[:4]):  # warm-up
+        mlmq.sssp(g, s, out=o, config=c, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for g, s, o, c in zip(graphs, srcs, seq, cfgs):
+        mlmq.sssp(g, s, out=o, config=c, stream=stream)
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    same = all(torch.equal(a, b) for a, b in zip(outs, seq))
+    import oracle
+    pick = [0, nrmat - 1, nrmat, nrmat + ngrid - 1]
+    exact = all(np.array_equal(mlmq.to_numpy(outs[i]), oracle.dijkstra(csrs[i], srcs[i])) for i in pick)
+    nq = nrmat + ngrid
+    res = dict(queries=nq, workload=f"{nrmat} sources RMAT-20 + {ngrid} sources grid1024 p0.05",
+               batch_s=t_batch, sequential_s=t_seq, batch_qps=nq / t_batch, sequential_qps=nq / t_seq,
+               speedup=t_seq / t_batch, statuses_ok=all(x == 0 for x in status),
+               batch_equals_sequential=same, oracle_checked=len(pick), oracle_equal=exact,
+               tuned={"rmat20": cr.as_dict(), "grid1024": cd.as_dict()})
+    log(f"[bench] batch: {nq} queries {t_batch:.3f}s ({nq / t_batch:.1f} q/s) vs sequential {t_seq:.3f}s "
+        f"({nq / t_seq:.1f} q/s), same={same} oracle={exact}")
+    for g in (gr, gd):
+        g.close()
+    return res
+
+
+def _percentiles(lat):
+    a = np.sort(np.asarray(lat))
+    return float(np.percentile(a, 50)), float(np.percentile(a, 99))
+
+
+def bench_serve(mlmq, torch, nreq, load, budget_gb, seed=7):
+    """Poisson arrivals over five resident graphs, served by the
+    continuous-batching server and, on the same trace, by a FIFO loop of plain
+    solves. Latency = completion - arrival."""
+    csrs = [gg.grid(512, 512, 0.05, seed=11), gg.grid(2048, 2048, 0.05, seed=12), gg.rmat(20, 16, seed=13),
+            gg.rmat(22, 16, seed=14), gg.uniform(1 << 22, 1 << 25, wmax=65535, seed=15)]
+    names = ["grid512", "grid2048", "rmat20", "rmat22", "uniform4M"]
+    graphs = [mlmq.Graph.from_csr(c) for c in csrs]
+    rng = np.random.default_rng(seed)
+    gid = rng.integers(0, len(csrs), nreq)
+    src = np.array([rng.integers(0, csrs[g].n) for g in gid])
+    stream = torch.cuda.current_stream()
+    per_graph = [mlmq.new_dist(c.n) for c in csrs]
+    # FIFO service rate, measured on the head of the trace
+    probe = min(nreq, 60)
+    for i in range(min(5, nreq)):
+        mlmq.sssp(graphs[gid[i]], int(src[i]), out=per_graph[gid[i]], stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(probe):
+        mlmq.sssp(graphs[gid[i]], int(src[i]), out=per_graph[gid[i]], stream=stream)
+    torch.cuda.synchronize()
+    mu = probe / (time.perf_counter() - t0)
+    lam = load * mu
+    arrive = np.cumsum(rng.exponential(1.0 / lam, nreq))
+    log(f"[bench] serve: FIFO service rate {mu:.1f} q/s, arrivals at {lam:.1f} q/s ({load}x)")
+
+    # FIFO loop of plain solves
+    fifo_lat, t_start = [], time.perf_counter()
+    keep = {}
+    for i in range(nreq):
+        now = time.perf_counter() - t_start
+        if now < arrive[i]:
+            time.sleep(arrive[i] - now)
+        g = gid[i]
+        mlmq.sssp(graphs[g], int(src[i]), out=per_graph[g], stream=stream)
+        torch.cuda.synchronize()
+        fifo_lat.append(time.perf_counter() - t_start - arrive[i])
+        if i % max(1, nreq // 8) == 0:
+            keep[i] = mlmq.to_numpy(per_graph[g]).copy()
+    fifo_span = time.perf_counter() - t_start - arrive[0]
+    log(f"[bench] serve: FIFO loop done in {fifo_span:.1f}s")
+
+    # continuous-batching server
+    outs = [mlmq.new_dist(csrs[g].n) for g in gid]
+    torch.cuda.synchronize()
+    srv = mlmq.Server(graphs, mem_budget_bytes=int(budget_gb * (1 << 30)), max_slots=64)
+    tickets, sub_ns = [], []
+    t_start = time.perf_counter()
+    try:
+        for i in range(nreq):
+            now = time.perf_counter() - t_start
+            if now < arrive[i]:
+                time.sleep(arrive[i] - now)
+            tickets.append(srv.submit(int(gid[i]), int(src[i]), outs[i]))
+        status = [srv.wait(t, 120000) for t in tickets]
+        times = [srv.times(t) for t in tickets]
+    finally:
+        srv.close()
+    t0_ns = times[0][0] - int(arrive[0] * 1e9)
+    srv_lat = [(b - t0_ns) / 1e9 - arrive[i] for i, (a, b) in enumerate(times)]
+    srv_span = (max(b for _, b in times) - t0_ns) / 1e9 - arrive[0]
+    same = all(np.array_equal(mlmq.to_numpy(outs[i]), keep[i]) for i in keep)
+    f50, f99 = _percentiles(fifo_lat)
+    s50, s99 = _percentiles(srv_lat)
+    res = dict(requests=nreq, graphs=names, arrival_rate_qps=lam, fifo_service_rate_qps=mu, load=load,
+               mem_budget_gb=budget_gb,
+               server_qps=nreq / srv_span, server_p50_ms=s50 * 1e3, server_p99_ms=s99 * 1e3,
+               fifo_qps=nreq / fifo_span, fifo_p50_ms=f50 * 1e3, fifo_p99_ms=f99 * 1e3,
+               statuses_ok=all(x == 0 for x in status), served_equals_alone=same, compared=len(keep))
+    log(f"[bench] serve: server {res['server_qps']:.1f} q/s p50 {res['server_p50_ms']:.2f} ms "
+        f"p99 {res['server_p99_ms']:.2f} ms | FIFO {res['fifo_qps']:.1f} q/s p50 {res['fifo_p50_ms']:.2f} ms "
+        f"p99 {res['fifo_p99_ms']:.2f} ms | same={same}")
+    for g in graphs:
+        g.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -127,6 +259,13 @@ def main():
     ap.add_argument("--config", default="", help="JSON overrides of the queue config (primary workload)")
     ap.add_argument("--also-config", default="", help="JSON overrides for the extra workloads")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch", type=int, default=1, help="run the batched-form comparison (0/1)")
+    ap.add_argument("--tune-ms", type=int, default=3000, help="autotuner budget per graph (batch)")
+    ap.add_argument("--serve", type=int, default=1000, help="serving requests (0 = skip)")
+    ap.add_argument("--serve-load", type=float, default=1.5, help="arrival rate / FIFO service rate")
+    ap.add_argument("--serve-budget-gb", type=float, default=8.0)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only run a plain device copy of this many MiB three times (calibrates HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
@@ -139,6 +278,17 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
     torch.cuda.set_device(0)
+
+    if args.copy_probe_mib:
+        nbytes = args.copy_probe_mib << 20
+        src = torch.empty(nbytes // 4, dtype=torch.int32, device="cuda").fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": nbytes, "copy_probe_bytes_written": nbytes, "launches": 3}))
+        return
 
     results = {}
     primary = None
@@ -161,6 +311,9 @@ def main():
             primary = s
         del csr, res
 
+    batch = bench_batch(mlmq, torch, args.tune_ms) if args.batch else None
+    serving = bench_serve(mlmq, torch, args.serve, args.serve_load, args.serve_budget_gb) if args.serve else None
+
     p = primary
     line = {
         "metric": METRIC,
@@ -181,6 +334,8 @@ def main():
                      "frac": p["achieved_gbs"] / HBM_PEAK_GBS, "traffic": None},
         "cpu_baseline": p.get("cpu_baseline"),
         "verified_against_oracle": p.get("verified_against_oracle"),
+        "batch": batch,
+        "serving": serving,
         "detail": {k: {kk: vv for kk, vv in v.items() if kk not in ("config",)} for k, v in results.items()},
     }
     print(json.dumps(line), flush=True)

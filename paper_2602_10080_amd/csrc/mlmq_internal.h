@@ -55,6 +55,7 @@ struct QueryCtrl {
   Word hub_units;  // hub chunks reserved (termination count)
   Word joined;     // workgroups that joined this query
   Word finished;   // workgroups that left this query
+  Word hungry;     // waves of this query that currently find no work
   uint64_t stats[16];  // [0, kNumCounters) used
 };
 

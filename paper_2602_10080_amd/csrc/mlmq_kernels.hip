@@ -138,6 +138,7 @@ struct Ctx {
   uint32_t it;               // loop iterations (heartbeat)
   bool stop;                 // leave the query (terminated or failed)
   bool ovf;                  // a candidate distance overflowed
+  bool hungry;               // this wave is counted in ctrl->hungry
   uint32_t ct[kNumCounters]; // per-wave counters
 };
 
@@ -380,7 +381,20 @@ __device__ __forceinline__ bool l2_read(Ctx& c, uint64_t& e, bool& ok) {
   while (mw) {
     const uint32_t j = first_lane(mw);
     mw &= mw - 1;
-    if (l2_try_ring(c, (cur + j) & (nr - 1u), lane_val(t, j), lane_val(h, j), e, ok)) return true;
+    if (l2_try_ring(c, (cur + j) & (nr - 1u), lane_val(t, j), lane_val(h, j), e, ok)) {
+      // The rings form a calendar: a ring read as bucket cur + j may still
+      // hold elements of a later lap (written when it was the catch-all last
+      // bucket). Those go back to the bucket they belong to now instead of
+      // being expanded ahead of the frontier.
+      const uint32_t b = elem_d(e) >> c.q.d2_log2;
+      const uint32_t rel = b <= cur ? 0u : min(b - cur, nr - 1u);
+      const bool later = ok && rel > j;
+      if (ballot(later)) {
+        l2_write(c, e, later);
+        ok = ok && !later;
+      }
+      return true;
+    }
   }
   return false;
 }
@@ -540,6 +554,30 @@ __device__ __forceinline__ void write_l1(Ctx& c, uint64_t e, bool ok) {
   c.ct[kCtL1Writes] += 1;
   if (ballot(spill)) l2_write(c, e, spill);
   if (flush) l1_flush(c);
+}
+
+// Work sharing between the levels: while other waves of the query find no
+// work, a wave whose L1 holds more than half a row hands half of it (far ring
+// first) to L2, where the idle waves pick it up. Without it a wave can keep a
+// whole wavefront in its private L1 (the near-far and filter queues never
+// overflow on low-degree graphs) while the rest of the grid waits.
+__device__ __forceinline__ void donate(Ctx& c) {
+  const uint32_t cnt = (c.qt - c.qh) + (c.ft - c.fh);
+  uint32_t give = cnt / 2u;
+  c.ct[kCtFlushes] += 1;
+  while (give && !c.stop) {
+    const bool from_far = c.ft != c.fh;
+    uint32_t& head = from_far ? c.fh : c.qh;
+    const uint32_t avail = from_far ? c.ft - c.fh : c.qt - c.qh;
+    const uint64_t* ring = from_far ? c.far : c.l1;
+    const uint32_t k = min(min(avail, 64u), give);
+    const bool ok = lane() < k;
+    const uint64_t x = ok ? ring[(head + lane()) & c.l1mask] : 0;
+    compiler_fence();
+    head += k;
+    give -= k;
+    l2_write(c, x, ok);
+  }
 }
 
 // L0 full: all of its elements move to L1 (Section 3.4, L0 queue).
@@ -739,6 +777,14 @@ __device__ __forceinline__ void refill_threshold(Ctx& c, uint32_t mn) {
   if (c.q.l1_type == MLMQ_L1_FILTER) c.thresh = sat_add(mn, c.q.delta1);
 }
 
+// Keeps ctrl->hungry equal to the number of this query's waves that found
+// no work on their last look.
+__device__ __forceinline__ void set_hungry(Ctx& c, bool h) {
+  if (c.hungry == h) return;
+  c.hungry = h;
+  if (lane() == 0) add32(&c.q.ctrl->hungry.v, h ? 1u : 0xFFFFFFFFu);
+}
+
 // The persistent worker loop of one wave on one query (the paper's work
 // kernel with the manager's emptiness test folded in).
 __device__ __forceinline__ void run_query(Ctx& c) {
@@ -753,12 +799,15 @@ __device__ __forceinline__ void run_query(Ctx& c) {
       l0_read(c, e, ok);
       got = true;
     } else if (c.q.l1_type != MLMQ_L1_NONE && !l1_empty(c)) {
+      if ((c.it & 15u) == 0 && (c.qt - c.qh) + (c.ft - c.fh) >= 32u && uni(ld32(&c.q.ctrl->hungry.v)) != 0)
+        donate(c);
       got = l1_take(c, e, ok);
       c.ct[kCtL1Reads] += 1;
     } else {
       uint32_t hv, hd, heb, hee;
       beat(c.beat, kPtHub, c.it);
       if (hub_claim(c, hv, hd, heb, hee)) {
+        set_hungry(c, false);
         c.done_acc += 1u;
         refill_threshold(c, hd);
         c.ct[kCtHubChunks] += 1;
@@ -769,6 +818,7 @@ __device__ __forceinline__ void run_query(Ctx& c) {
       beat(c.beat, kPtL2Read, c.it);
       got = l2_read(c, e, ok);
       if (got) {
+        set_hungry(c, false);
         c.done_acc += 1u;
         refill_threshold(c, uni(wave_min(ok ? elem_d(e) : kInf)));
       } else {
@@ -781,6 +831,7 @@ __device__ __forceinline__ void run_query(Ctx& c) {
           vm_drain();
           c.done_acc = 0;
         }
+        set_hungry(c, true);
         if (try_terminate(c)) break;
         if ((++idle & 7u) == 0 && must_stop(c)) break;
         backoff(min(idle >> 2, 6u));
@@ -791,6 +842,7 @@ __device__ __forceinline__ void run_query(Ctx& c) {
     beat(c.beat, kPtProcess, c.it);
     process_vec(c, e, ok);
   }
+  set_hungry(c, false);
   beat(c.beat, kPtDone, c.it);
 }
 
@@ -837,6 +889,7 @@ __device__ __forceinline__ void setup_ctx(Ctx& c, const QueryDesc& q, uint64_t* 
   c.it = 0;
   c.stop = false;
   c.ovf = false;
+  c.hungry = false;
 #pragma unroll
   for (int i = 0; i < kNumCounters; ++i) c.ct[i] = 0;
 }

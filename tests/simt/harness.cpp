@@ -115,7 +115,8 @@ extern "C" int sim_sssp(int32_t n, const int32_t* off, const int32_t* col, const
   a.waves = waves;
   a.timeout_ticks = (uint64_t)k[14] * 100000ull;
   a.cap_wait_ticks = 200ull * 100000ull;
-  a.beats = nullptr;
+  std::vector<uint32_t> beats(nwg * waves, 0);
+  a.beats = getenv("SIM_DUMP") ? beats.data() : nullptr;
   std::vector<simt::Wave*> wv;
   std::vector<simt::Group> grp(nwg);
   std::vector<std::barrier<>*> bars;
@@ -142,9 +143,13 @@ extern "C" int sim_sssp(int32_t n, const int32_t* off, const int32_t* col, const
         mlmq_worker(a);
       });
   for (auto& t : th) t.join();
-  if (getenv("SIM_DUMP"))
-    fprintf(stderr, "ring0 tail %u head %u done %u term %u err %u\n", rings[0].tail.v, rings[0].head.v,
-            ctrl->done.v, ctrl->terminate.v, ctrl->error.v);
+  if (getenv("SIM_DUMP")) {
+    fprintf(stderr, "done %u term %u err %u cur %u hub_units %u\n", ctrl->done.v, ctrl->terminate.v, ctrl->error.v,
+            ctrl->cur.v, ctrl->hub_units.v);
+    for (uint32_t r = 0; r < nrings; ++r)
+      if (rings[r].tail.v || rings[r].head.v) fprintf(stderr, "  ring %u tail %u head %u\n", r, rings[r].tail.v, rings[r].head.v);
+    for (uint32_t i = 0; i < nwg * waves; ++i) fprintf(stderr, "  wave %u point %u it %u\n", i, beats[i] >> 24, beats[i] & 0xFFFFFF);
+  }
   for (int i = 0; i < kNumCounters && stats; ++i) stats[i] = ctrl->stats[i];
   if (status) {
     status[0] = ctrl->error.v;

@@ -155,7 +155,7 @@ inline int __popcll(unsigned long long m) { return __builtin_popcountll(m); }
 inline int __ffsll(long long m) { return __builtin_ffsll(m); }
 inline void __syncthreads() { simt::group->bar->arrive_and_wait(); }
 inline void __builtin_amdgcn_wave_barrier() { simt::wave_sync(); }
-#define __builtin_amdgcn_s_sleep(n) std::this_thread::yield()
+#define __builtin_amdgcn_s_sleep(n) std::this_thread::sleep_for(std::chrono::microseconds(4 * (n)))
 // The GPU reads its clock with a scalar instruction, one value per wave; so
 // does this: lane 0 reads, every lane gets its value.
 inline long long wall_clock64() {
