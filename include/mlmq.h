@@ -74,6 +74,9 @@ typedef struct mlmq_stats {
   uint64_t flushes;        /* L1V periodic flushes */
   uint32_t grid_wgs;       /* workgroups launched */
   uint32_t retries;        /* capacity retries taken */
+  uint64_t donations;      /* L1 backlogs handed to L2 for idle waves */
+  double wave_ms;          /* summed over waves: time spent on the query */
+  double idle_ms;          /* summed over waves: time with no work at any level */
 } mlmq_stats;
 
 /*

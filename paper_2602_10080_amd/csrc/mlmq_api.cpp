@@ -549,6 +549,9 @@ void fill_stats(mlmq_stats* st, const QueryCtrl& h, double ms, double worker_ms,
   st->l2_reads = h.stats[kCtL2Reads];
   st->hub_chunks = h.stats[kCtHubChunks];
   st->flushes = h.stats[kCtFlushes];
+  st->donations = h.stats[kCtDonations];
+  st->wave_ms = (double)h.stats[kCtWaveTicks] / (double)device_info()->ticks_per_ms;
+  st->idle_ms = (double)h.stats[kCtIdleTicks] / (double)device_info()->ticks_per_ms;
   st->grid_wgs = grid;
   st->retries = retries;
 }

@@ -33,6 +33,9 @@ enum : int {
   kCtL2Reads,
   kCtHubChunks,
   kCtFlushes,
+  kCtDonations,
+  kCtWaveTicks,  // wall-clock ticks the waves spent on the query
+  kCtIdleTicks,  // of which with no work at any level
   kNumCounters
 };
 

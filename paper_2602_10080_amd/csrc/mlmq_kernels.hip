@@ -139,6 +139,7 @@ struct Ctx {
   bool stop;                 // leave the query (terminated or failed)
   bool ovf;                  // a candidate distance overflowed
   bool hungry;               // this wave is counted in ctrl->hungry
+  uint64_t ct64_wave, ct64_idle;  // ticks on the query / idle (set when it ends)
   uint32_t ct[kNumCounters]; // per-wave counters
 };
 
@@ -564,7 +565,7 @@ __device__ __forceinline__ void write_l1(Ctx& c, uint64_t e, bool ok) {
 __device__ __forceinline__ void donate(Ctx& c) {
   const uint32_t cnt = (c.qt - c.qh) + (c.ft - c.fh);
   uint32_t give = cnt / 2u;
-  c.ct[kCtFlushes] += 1;
+  c.ct[kCtDonations] += 1;
   while (give && !c.stop) {
     const bool from_far = c.ft != c.fh;
     uint32_t& head = from_far ? c.fh : c.qh;
@@ -789,6 +790,8 @@ __device__ __forceinline__ void set_hungry(Ctx& c, bool h) {
 // kernel with the manager's emptiness test folded in).
 __device__ __forceinline__ void run_query(Ctx& c) {
   uint32_t idle = 0;
+  const uint64_t t_start = (uint64_t)wall_clock64();
+  uint64_t t_idle = 0;
   while (!c.stop) {
     ++c.it;
     beat(c.beat, kPtLoop, c.it);
@@ -824,6 +827,7 @@ __device__ __forceinline__ void run_query(Ctx& c) {
       } else {
         // Idle: the wave holds nothing, so its delayed count can go out.
         beat(c.beat, kPtIdle, c.it);
+        const uint64_t t0 = (uint64_t)wall_clock64();
         if (c.done_acc) {
           uint32_t r = 0;
           if (lane() == 0) r = add32(&c.q.ctrl->done.v, c.done_acc);
@@ -835,6 +839,7 @@ __device__ __forceinline__ void run_query(Ctx& c) {
         if (try_terminate(c)) break;
         if ((++idle & 7u) == 0 && must_stop(c)) break;
         backoff(min(idle >> 2, 6u));
+        t_idle += (uint64_t)wall_clock64() - t0;
         continue;
       }
     }
@@ -843,6 +848,8 @@ __device__ __forceinline__ void run_query(Ctx& c) {
     process_vec(c, e, ok);
   }
   set_hungry(c, false);
+  c.ct64_wave = (uint64_t)wall_clock64() - t_start;
+  c.ct64_idle = t_idle;
   beat(c.beat, kPtDone, c.it);
 }
 
@@ -890,6 +897,7 @@ __device__ __forceinline__ void setup_ctx(Ctx& c, const QueryDesc& q, uint64_t* 
   c.stop = false;
   c.ovf = false;
   c.hungry = false;
+  c.ct64_wave = c.ct64_idle = 0;
 #pragma unroll
   for (int i = 0; i < kNumCounters; ++i) c.ct[i] = 0;
 }
@@ -899,8 +907,10 @@ __device__ __forceinline__ void flush_counters(const Ctx& c) {
   if (lane() == 0) {
     QueryCtrl* ctl = c.q.ctrl;
 #pragma unroll
-    for (int i = 0; i < kNumCounters; ++i)
+    for (int i = 0; i < kCtWaveTicks; ++i)
       if (c.ct[i]) __hip_atomic_fetch_add(&ctl->stats[i], (uint64_t)c.ct[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(&ctl->stats[kCtWaveTicks], c.ct64_wave, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(&ctl->stats[kCtIdleTicks], c.ct64_idle, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (c.ovf) st32(&ctl->overflow.v, 1u);
   }
 }
