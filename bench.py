@@ -154,7 +154,19 @@ def bench_batch(mlmq, torch, tune_ms, nrmat=256, ngrid=64):
     pick = [0, nrmat - 1, nrmat, nrmat + ngrid - 1]
     exact = all(np.array_equal(mlmq.to_numpy(outs[i]), oracle.dijkstra(csrs[i], srcs[i])) for i in pick)
     nq = nrmat + ngrid
-    res = dict(queries=nq, workload=f"{nrmat} sources RMAT-20 + {ngrid} sources grid1024 p0.05",
+    # CPU baseline: the oracle, one query per thread over all host cores, on a
+    # sample of the batch in the same RMAT/grid proportion
+    from concurrent.futures import ThreadPoolExecutor
+    cores = min(16, os.cpu_count() or 1)  # the host share of one GPU
+    sample = list(range(0, nrmat, max(1, nrmat // 16)))[:16] + list(range(nrmat, nq, max(1, ngrid // 4)))[:4]
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=cores) as ex:
+        list(ex.map(lambda i: oracle.dijkstra(csrs[i], srcs[i]), sample))
+    t_cpu = time.perf_counter() - t0
+    cpu = dict(value=len(sample) / t_cpu, unit="queries/s", cores=cores, kind="oracle",
+               sample=f"{len(sample)} of the batch's queries ({sum(1 for i in sample if i < nrmat)} RMAT-20, "
+                      f"{sum(1 for i in sample if i >= nrmat)} grid1024), one per thread")
+    res = dict(queries=nq, cpu_baseline=cpu, workload=f"{nrmat} sources RMAT-20 + {ngrid} sources grid1024 p0.05",
                batch_s=t_batch, sequential_s=t_seq, batch_qps=nq / t_batch, sequential_qps=nq / t_seq,
                speedup=t_seq / t_batch, statuses_ok=all(x == 0 for x in status),
                batch_equals_sequential=same, oracle_checked=len(pick), oracle_equal=exact,

@@ -59,6 +59,7 @@ struct QueryCtrl {
   Word joined;     // workgroups that joined this query
   Word finished;   // workgroups that left this query
   Word hungry;     // waves of this query that currently find no work
+  Word active;     // waves currently working on this query
   uint64_t stats[16];  // [0, kNumCounters) used
 };
 

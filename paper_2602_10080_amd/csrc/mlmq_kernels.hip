@@ -376,8 +376,15 @@ __device__ __forceinline__ bool l2_read(Ctx& c, uint64_t& e, bool& ok) {
   }
   const uint32_t pend_r = __shfl(c.pend, (int)r);
   const uint64_t m = ballot(in && (pend_r != kInf || (int32_t)(t - h) > 0));
-  // base moves to the first non-empty bucket when the head bucket is empty
-  if (m && !(m & 1u) && lane() == 0) cas32(&c.q.ctrl->cur.v, cur, cur + first_lane(m));
+  // The base moves to the first non-empty bucket once the head bucket is
+  // empty and no wave holds work in its own L0/L1 (all are idle): work held
+  // privately is part of the head bucket too, and moving on without it would
+  // let the whole grid run ahead of the frontier.
+  if (m && !(m & 1u)) {
+    const uint32_t hungry = uni(ld32(&c.q.ctrl->hungry.v));
+    const uint32_t act = uni(ld32(&c.q.ctrl->active.v));
+    if (hungry >= act && lane() == 0) cas32(&c.q.ctrl->cur.v, cur, cur + first_lane(m));
+  }
   uint64_t mw = m & (c.q.bnum >= 64 ? ~0ull : ((1ull << c.q.bnum) - 1ull));
   while (mw) {
     const uint32_t j = first_lane(mw);
@@ -558,24 +565,20 @@ __device__ __forceinline__ void write_l1(Ctx& c, uint64_t e, bool ok) {
 }
 
 // Work sharing between the levels: while other waves of the query find no
-// work, a wave whose L1 holds more than half a row hands half of it (far ring
-// first) to L2, where the idle waves pick it up. Without it a wave can keep a
-// whole wavefront in its private L1 (the near-far and filter queues never
-// overflow on low-degree graphs) while the rest of the grid waits.
+// work, a wave whose L1 main (near) ring holds more than half a row hands the
+// older half of it to L2, where the idle waves pick it up; the far ring stays
+// private, since handing it out would put work ahead of the frontier. Without
+// this a wave can keep a whole wavefront in its private L1 (the near-far and
+// filter queues never overflow on low-degree graphs) while the grid waits.
 __device__ __forceinline__ void donate(Ctx& c) {
-  const uint32_t cnt = (c.qt - c.qh) + (c.ft - c.fh);
-  uint32_t give = cnt / 2u;
+  uint32_t give = (c.qt - c.qh) / 2u;
   c.ct[kCtDonations] += 1;
   while (give && !c.stop) {
-    const bool from_far = c.ft != c.fh;
-    uint32_t& head = from_far ? c.fh : c.qh;
-    const uint32_t avail = from_far ? c.ft - c.fh : c.qt - c.qh;
-    const uint64_t* ring = from_far ? c.far : c.l1;
-    const uint32_t k = min(min(avail, 64u), give);
+    const uint32_t k = min(give, 64u);
     const bool ok = lane() < k;
-    const uint64_t x = ok ? ring[(head + lane()) & c.l1mask] : 0;
+    const uint64_t x = ok ? c.l1[(c.qh + lane()) & c.l1mask] : 0;
     compiler_fence();
-    head += k;
+    c.qh += k;
     give -= k;
     l2_write(c, x, ok);
   }
@@ -792,6 +795,7 @@ __device__ __forceinline__ void run_query(Ctx& c) {
   uint32_t idle = 0;
   const uint64_t t_start = (uint64_t)wall_clock64();
   uint64_t t_idle = 0;
+  if (lane() == 0) add32(&c.q.ctrl->active.v, 1u);
   while (!c.stop) {
     ++c.it;
     beat(c.beat, kPtLoop, c.it);
@@ -802,7 +806,7 @@ __device__ __forceinline__ void run_query(Ctx& c) {
       l0_read(c, e, ok);
       got = true;
     } else if (c.q.l1_type != MLMQ_L1_NONE && !l1_empty(c)) {
-      if ((c.it & 15u) == 0 && (c.qt - c.qh) + (c.ft - c.fh) >= 32u && uni(ld32(&c.q.ctrl->hungry.v)) != 0)
+      if ((c.it & 15u) == 0 && c.qt - c.qh >= 32u && uni(ld32(&c.q.ctrl->hungry.v)) != 0)
         donate(c);
       got = l1_take(c, e, ok);
       c.ct[kCtL1Reads] += 1;
@@ -848,6 +852,7 @@ __device__ __forceinline__ void run_query(Ctx& c) {
     process_vec(c, e, ok);
   }
   set_hungry(c, false);
+  if (lane() == 0) add32(&c.q.ctrl->active.v, 0xFFFFFFFFu);
   c.ct64_wave = (uint64_t)wall_clock64() - t_start;
   c.ct64_idle = t_idle;
   beat(c.beat, kPtDone, c.it);
