@@ -75,6 +75,7 @@ typedef struct mlmq_stats {
   uint32_t grid_wgs;       /* workgroups launched */
   uint32_t retries;        /* capacity retries taken */
   uint64_t donations;      /* L1 backlogs handed to L2 for idle waves */
+  uint64_t atomics;        /* atomicMin issued (candidates that passed the label pre-check) */
   double wave_ms;          /* summed over waves: time spent on the query */
   double idle_ms;          /* summed over waves: time with no work at any level */
 } mlmq_stats;

@@ -55,7 +55,8 @@ class Stats(ctypes.Structure):
         ("pushes", ctypes.c_uint64), ("l1_writes", ctypes.c_uint64), ("l1_reads", ctypes.c_uint64),
         ("l2_writes", ctypes.c_uint64), ("l2_reads", ctypes.c_uint64), ("hub_chunks", ctypes.c_uint64),
         ("flushes", ctypes.c_uint64), ("grid_wgs", ctypes.c_uint32), ("retries", ctypes.c_uint32),
-        ("donations", ctypes.c_uint64), ("wave_ms", ctypes.c_double), ("idle_ms", ctypes.c_double),
+        ("donations", ctypes.c_uint64), ("atomics", ctypes.c_uint64), ("wave_ms", ctypes.c_double),
+        ("idle_ms", ctypes.c_double),
     ]
 
     def as_dict(self) -> dict:

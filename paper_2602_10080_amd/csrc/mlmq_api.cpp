@@ -550,6 +550,7 @@ void fill_stats(mlmq_stats* st, const QueryCtrl& h, double ms, double worker_ms,
   st->hub_chunks = h.stats[kCtHubChunks];
   st->flushes = h.stats[kCtFlushes];
   st->donations = h.stats[kCtDonations];
+  st->atomics = h.stats[kCtAtomics];
   st->wave_ms = (double)h.stats[kCtWaveTicks] / (double)device_info()->ticks_per_ms;
   st->idle_ms = (double)h.stats[kCtIdleTicks] / (double)device_info()->ticks_per_ms;
   st->grid_wgs = grid;

@@ -34,6 +34,7 @@ enum : int {
   kCtHubChunks,
   kCtFlushes,
   kCtDonations,
+  kCtAtomics,    // atomicMin issued (candidates that passed the label pre-check)
   kCtWaveTicks,  // wall-clock ticks the waves spent on the query
   kCtIdleTicks,  // of which with no work at any level
   kNumCounters

@@ -646,6 +646,10 @@ __device__ __forceinline__ void relax_many(Ctx& c, const bool (&has)[U], const u
     lab[u] = ld_label(c.q.dist + lv);
   }
   bool imp[U];
+  uint32_t natom = 0;
+#pragma unroll
+  for (int u = 0; u < U; ++u) natom += popc(ballot(cand[u] && nd[u] < lab[u]));
+  c.ct[kCtAtomics] += natom;
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     imp[u] = false;

@@ -37,7 +37,7 @@ def test_library_exports_every_declared_symbol():
 def test_struct_sizes_match_header():
     mlmq = _mlmq()
     assert ctypes.sizeof(mlmq.Config) == 88
-    assert ctypes.sizeof(mlmq.Stats) == 136
+    assert ctypes.sizeof(mlmq.Stats) == 144
     assert ctypes.sizeof(mlmq.Features) == 64
 
 
