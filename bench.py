@@ -53,6 +53,25 @@ def make_workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
+KERNEL_SRC = os.path.join(ROOT, "paper_2602_10080_amd", "csrc", "mlmq_kernels.hip")
+
+
+def measured_traffic(workload):
+    """HBM bytes per launch of the persistent kernel from the committed
+    rocprofv3 counter summary for this workload (FETCH_SIZE + WRITE_SIZE, each
+    scaled by the same counter's reading for a copy of known size), or None if
+    there is none or the kernel source changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"traffic_mlmq_worker_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    if rec.get("kernel_sha256") != sha:
+        return None
+    return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+
+
 def reach(csr, dist):
     fin = dist != INF
     return int(fin.sum()), int(csr.degrees()[fin].sum())
@@ -343,7 +362,7 @@ def main():
         "config": {"workload": p["workload"], "graph": p["description"], "n": p["n"], "m": p["m"],
                    "source": p["source"], "queues": p["config"]},
         "roofline": {"bound": "hbm", "achieved": p["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": p["achieved_gbs"] / HBM_PEAK_GBS, "traffic": None},
+                     "frac": p["achieved_gbs"] / HBM_PEAK_GBS, "traffic": measured_traffic(p["workload"])},
         "cpu_baseline": p.get("cpu_baseline"),
         "verified_against_oracle": p.get("verified_against_oracle"),
         "batch": batch,

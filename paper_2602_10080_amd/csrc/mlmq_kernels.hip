@@ -139,6 +139,7 @@ struct Ctx {
   bool stop;                 // leave the query (terminated or failed)
   bool ovf;                  // a candidate distance overflowed
   bool hungry;               // this wave is counted in ctrl->hungry
+  uint32_t idle;             // consecutive loop iterations without work
   uint64_t ct64_wave, ct64_idle;  // ticks on the query / idle (set when it ends)
   uint32_t ct[kNumCounters]; // per-wave counters
 };
@@ -314,8 +315,10 @@ __device__ __forceinline__ bool l2_take(Ctx& c, uint32_t ring, uint32_t t, uint6
 
 // Read from one ring: keep a claimed ticket across READ_EMPTY (Section 4.2),
 // else claim the oldest unread one. With few blocks available the claim is a
-// compare-and-swap that never overshoots the writers; with many it is one
-// atomicAdd, whose rare overshoot leaves a pending claim for later.
+// compare-and-swap that never overshoots the writers; with many (FIFO only)
+// it is one atomicAdd, whose rare overshoot leaves a pending claim for later.
+// Bucket rings always claim by compare-and-swap, so a pending claim there is
+// always a block whose writer is about to publish it.
 __device__ __forceinline__ bool l2_try_ring(Ctx& c, uint32_t ring, uint32_t t_seen, uint32_t h_seen, uint64_t& e,
                                             bool& ok) {
   uint32_t p = lane_val(c.pend, ring);
@@ -323,7 +326,7 @@ __device__ __forceinline__ bool l2_try_ring(Ctx& c, uint32_t ring, uint32_t t_se
     RingCtr* rc = c.q.rings + ring;
     uint32_t claimed = 0;
     if (lane() == 0) {
-      if ((int32_t)(t_seen - h_seen) > 64) {
+      if (c.q.nrings == 1 && (int32_t)(t_seen - h_seen) > 64) {
         p = add32(&rc->head.v, 1u);
         claimed = 1;
       } else {
@@ -353,6 +356,20 @@ __device__ __forceinline__ bool l2_try_ring(Ctx& c, uint32_t ring, uint32_t t_se
   return false;
 }
 
+// The bucket rings form a calendar: a ring read as bucket cur + j may still
+// hold elements of a later lap (written when it was the catch-all last
+// bucket). Those go back to the bucket they belong to now instead of being
+// expanded ahead of the frontier.
+__device__ __forceinline__ void defer_later(Ctx& c, uint32_t cur, uint32_t j, uint64_t e, bool& ok) {
+  const uint32_t b = elem_d(e) >> c.q.d2_log2;
+  const uint32_t rel = b <= cur ? 0u : min(b - cur, c.q.nrings - 1u);
+  const bool later = ok && rel > j;
+  if (ballot(later)) {
+    l2_write(c, e, later);
+    ok = ok && !later;
+  }
+}
+
 // L2 Read.
 __device__ __forceinline__ bool l2_read(Ctx& c, uint64_t& e, bool& ok) {
   if (c.q.nrings == 1) {
@@ -364,9 +381,19 @@ __device__ __forceinline__ bool l2_read(Ctx& c, uint64_t& e, bool& ok) {
     }
     return l2_try_ring(c, 0, t, h, e, ok);
   }
-  // Bucket queue: lane i looks at bucket cur + i; scan the first bnum.
+  // Bucket queue.
   const uint32_t nr = c.q.nrings;
   const uint32_t cur = uni(ld32(&c.q.ctrl->cur.v));
+  // A block this wave already claimed is taken first, wherever its ring now
+  // sits in the calendar (its writer is publishing it).
+  const uint64_t pm = ballot(lane() < nr && c.pend != kInf);
+  if (pm) {
+    const uint32_t r = first_lane(pm);
+    if (!l2_try_ring(c, r, 0, 0, e, ok)) return false;
+    defer_later(c, cur, (r - cur) & (nr - 1u), e, ok);
+    return true;
+  }
+  // lane i looks at bucket cur + i
   const bool in = lane() < nr;
   const uint32_t r = (cur + lane()) & (nr - 1u);
   uint32_t t = 0, h = 0;
@@ -374,33 +401,27 @@ __device__ __forceinline__ bool l2_read(Ctx& c, uint64_t& e, bool& ok) {
     t = ld32(&c.q.rings[r].tail.v);
     h = ld32(&c.q.rings[r].head.v);
   }
-  const uint32_t pend_r = __shfl(c.pend, (int)r);
-  const uint64_t m = ballot(in && (pend_r != kInf || (int32_t)(t - h) > 0));
+  const uint64_t m = ballot(in && (int32_t)(t - h) > 0);
   // The base moves to the first non-empty bucket once the head bucket is
   // empty and no wave holds work in its own L0/L1 (all are idle): work held
-  // privately is part of the head bucket too, and moving on without it would
-  // let the whole grid run ahead of the frontier.
+  // privately is part of the head bucket too, and moving on without it lets
+  // the grid run ahead of the frontier. A wave that has found nothing for a
+  // while moves it anyway, which bounds the wait when local queues stay busy.
   if (m && !(m & 1u)) {
-    const uint32_t hungry = uni(ld32(&c.q.ctrl->hungry.v));
-    const uint32_t act = uni(ld32(&c.q.ctrl->active.v));
-    if (hungry >= act && lane() == 0) cas32(&c.q.ctrl->cur.v, cur, cur + first_lane(m));
+    bool go = c.idle >= 32u;
+    if (!go) {
+      const uint32_t hungry = uni(ld32(&c.q.ctrl->hungry.v));
+      const uint32_t act = uni(ld32(&c.q.ctrl->active.v));
+      go = hungry >= act;
+    }
+    if (go && lane() == 0) cas32(&c.q.ctrl->cur.v, cur, cur + first_lane(m));
   }
   uint64_t mw = m & (c.q.bnum >= 64 ? ~0ull : ((1ull << c.q.bnum) - 1ull));
   while (mw) {
     const uint32_t j = first_lane(mw);
     mw &= mw - 1;
     if (l2_try_ring(c, (cur + j) & (nr - 1u), lane_val(t, j), lane_val(h, j), e, ok)) {
-      // The rings form a calendar: a ring read as bucket cur + j may still
-      // hold elements of a later lap (written when it was the catch-all last
-      // bucket). Those go back to the bucket they belong to now instead of
-      // being expanded ahead of the frontier.
-      const uint32_t b = elem_d(e) >> c.q.d2_log2;
-      const uint32_t rel = b <= cur ? 0u : min(b - cur, nr - 1u);
-      const bool later = ok && rel > j;
-      if (ballot(later)) {
-        l2_write(c, e, later);
-        ok = ok && !later;
-      }
+      defer_later(c, cur, j, e, ok);
       return true;
     }
   }
@@ -796,7 +817,6 @@ __device__ __forceinline__ void set_hungry(Ctx& c, bool h) {
 // The persistent worker loop of one wave on one query (the paper's work
 // kernel with the manager's emptiness test folded in).
 __device__ __forceinline__ void run_query(Ctx& c) {
-  uint32_t idle = 0;
   const uint64_t t_start = (uint64_t)wall_clock64();
   uint64_t t_idle = 0;
   if (lane() == 0) add32(&c.q.ctrl->active.v, 1u);
@@ -822,7 +842,7 @@ __device__ __forceinline__ void run_query(Ctx& c) {
         c.done_acc += 1u;
         refill_threshold(c, hd);
         c.ct[kCtHubChunks] += 1;
-        idle = 0;
+        c.idle = 0;
         if (hd <= uni(ld_label(c.q.dist + hv))) process_range(c, hd, heb, hee);
         continue;
       }
@@ -845,13 +865,13 @@ __device__ __forceinline__ void run_query(Ctx& c) {
         }
         set_hungry(c, true);
         if (try_terminate(c)) break;
-        if ((++idle & 7u) == 0 && must_stop(c)) break;
-        backoff(min(idle >> 2, 6u));
+        if ((++c.idle & 7u) == 0 && must_stop(c)) break;
+        backoff(min(c.idle >> 2, 6u));
         t_idle += (uint64_t)wall_clock64() - t0;
         continue;
       }
     }
-    idle = 0;
+    c.idle = 0;
     beat(c.beat, kPtProcess, c.it);
     process_vec(c, e, ok);
   }
@@ -906,6 +926,7 @@ __device__ __forceinline__ void setup_ctx(Ctx& c, const QueryDesc& q, uint64_t* 
   c.stop = false;
   c.ovf = false;
   c.hungry = false;
+  c.idle = 0;
   c.ct64_wave = c.ct64_idle = 0;
 #pragma unroll
   for (int i = 0; i < kNumCounters; ++i) c.ct[i] = 0;
