@@ -515,6 +515,42 @@ static bool is_device_ptr(const void* p) {
   return at.type == hipMemoryTypeDevice || at.type == hipMemoryTypeManaged;
 }
 
+// Queue counters of a finished (or stopped) query, for error messages.
+std::string describe_query_state(const QueryDesc& d, const uint32_t* d_beats, uint32_t nbeats) {
+  QueryCtrl hc;
+  std::vector<RingCtr> hr(d.nrings);
+  if (hipMemcpy(&hc, d.ctrl, sizeof(hc), hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(hr.data(), d.rings, sizeof(RingCtr) * d.nrings, hipMemcpyDeviceToHost) != hipSuccess) {
+    (void)hipGetLastError();
+    return "queue state unreadable";
+  }
+  uint64_t reserved = hc.hub_units.v;
+  for (const RingCtr& r : hr) reserved += r.tail.v;
+  char buf[256];
+  snprintf(buf, sizeof(buf), "done %u reserved %llu cur %u hungry %u active %u hub %u/%u; tail/head:", hc.done.v,
+           (unsigned long long)reserved, hc.cur.v, hc.hungry.v, hc.active.v, hc.hub_head.v, hc.hub_tail.v);
+  std::string out = buf;
+  for (uint32_t i = 0; i < d.nrings && i < 64; ++i) {
+    if (!hr[i].tail.v && !hr[i].head.v) continue;
+    snprintf(buf, sizeof(buf), " r%u=%u/%u", i, hr[i].tail.v, hr[i].head.v);
+    out += buf;
+  }
+  if (d_beats && nbeats) {
+    std::vector<uint32_t> hb(nbeats);
+    if (hipMemcpy(hb.data(), d_beats, 4ull * nbeats, hipMemcpyDeviceToHost) == hipSuccess) {
+      uint32_t hist[16] = {0};
+      for (uint32_t b : hb) hist[(b >> 24) & 15u] += 1;
+      out += "; waves by last program point:";
+      for (int p = 0; p < 16; ++p)
+        if (hist[p]) {
+          snprintf(buf, sizeof(buf), " p%d=%u", p, hist[p]);
+          out += buf;
+        }
+    }
+  }
+  return out;
+}
+
 int status_to_code(uint32_t st) {
   switch (st) {
     case kStOk:
@@ -749,7 +785,8 @@ int run_single(const mlmq_graph* g, uint32_t source, uint32_t* dist_out, const m
       }
       if (*h_flag) rc = set_error(MLMQ_ERR_DISTANCE_OVERFLOW, "a reachable distance does not fit below 2^32-1");
     } else if (rc != MLMQ_OK) {
-      set_error(rc, "solve failed with device status %u", st);
+      const std::string state = describe_query_state(*h_desc, d_beats, shape.grid);
+      set_error(rc, "solve failed with device status %u (%s)", st, state.c_str());
     }
     if (!dev_out && (rc == MLMQ_OK || rc == MLMQ_ERR_DISTANCE_OVERFLOW)) {
       e = hipMemcpyAsync(dist_out, d_dist, 4ull * g->n, hipMemcpyDeviceToHost, stream);

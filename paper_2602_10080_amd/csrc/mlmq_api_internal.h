@@ -80,6 +80,7 @@ int launch_shape(const mlmq_config& c, uint32_t l1_cap, bool two, LaunchShape* o
 LaunchArgs make_args(const QueryDesc* d_desc, BatchCtrl* d_batch, int nq, const LaunchShape& s, uint32_t timeout_ms,
                      uint32_t* d_beats);
 int status_to_code(uint32_t st);
+std::string describe_query_state(const QueryDesc& d, const uint32_t* d_beats, uint32_t nbeats);
 void fill_stats(mlmq_stats* st, const QueryCtrl& h, double ms, double worker_ms, uint32_t grid, uint32_t retries);
 int run_single(const mlmq_graph* g, uint32_t source, uint32_t* dist_out, const mlmq_config& c);
 // What the host watchdog snapshots when a launch overruns its deadline.

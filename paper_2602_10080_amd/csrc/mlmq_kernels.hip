@@ -315,10 +315,9 @@ __device__ __forceinline__ bool l2_take(Ctx& c, uint32_t ring, uint32_t t, uint6
 
 // Read from one ring: keep a claimed ticket across READ_EMPTY (Section 4.2),
 // else claim the oldest unread one. With few blocks available the claim is a
-// compare-and-swap that never overshoots the writers; with many (FIFO only)
-// it is one atomicAdd, whose rare overshoot leaves a pending claim for later.
-// Bucket rings always claim by compare-and-swap, so a pending claim there is
-// always a block whose writer is about to publish it.
+// compare-and-swap that never overshoots the writers; with many it is one
+// atomicAdd (thousands of waves compare-and-swapping one counter serialise),
+// whose rare overshoot leaves a pending claim that a later write fills.
 __device__ __forceinline__ bool l2_try_ring(Ctx& c, uint32_t ring, uint32_t t_seen, uint32_t h_seen, uint64_t& e,
                                             bool& ok) {
   uint32_t p = lane_val(c.pend, ring);
@@ -326,7 +325,7 @@ __device__ __forceinline__ bool l2_try_ring(Ctx& c, uint32_t ring, uint32_t t_se
     RingCtr* rc = c.q.rings + ring;
     uint32_t claimed = 0;
     if (lane() == 0) {
-      if (c.q.nrings == 1 && (int32_t)(t_seen - h_seen) > 64) {
+      if ((int32_t)(t_seen - h_seen) > 64) {
         p = add32(&rc->head.v, 1u);
         claimed = 1;
       } else {
@@ -384,14 +383,18 @@ __device__ __forceinline__ bool l2_read(Ctx& c, uint64_t& e, bool& ok) {
   // Bucket queue.
   const uint32_t nr = c.q.nrings;
   const uint32_t cur = uni(ld32(&c.q.ctrl->cur.v));
-  // A block this wave already claimed is taken first, wherever its ring now
-  // sits in the calendar (its writer is publishing it).
+  // Blocks this wave already claimed are taken first, wherever their rings
+  // now sit in the calendar. A claim whose block is not written yet does not
+  // stop the wave from reading other rings: if every wave waited on such a
+  // claim, nobody would produce the writes that fill them.
   const uint64_t pm = ballot(lane() < nr && c.pend != kInf);
-  if (pm) {
-    const uint32_t r = first_lane(pm);
-    if (!l2_try_ring(c, r, 0, 0, e, ok)) return false;
-    defer_later(c, cur, (r - cur) & (nr - 1u), e, ok);
-    return true;
+  for (uint64_t mp = pm; mp;) {
+    const uint32_t r = first_lane(mp);
+    mp &= mp - 1;
+    if (l2_try_ring(c, r, 0, 0, e, ok)) {
+      defer_later(c, cur, (r - cur) & (nr - 1u), e, ok);
+      return true;
+    }
   }
   // lane i looks at bucket cur + i
   const bool in = lane() < nr;
@@ -416,7 +419,10 @@ __device__ __forceinline__ bool l2_read(Ctx& c, uint64_t& e, bool& ok) {
     }
     if (go && lane() == 0) cas32(&c.q.ctrl->cur.v, cur, cur + first_lane(m));
   }
-  uint64_t mw = m & (c.q.bnum >= 64 ? ~0ull : ((1ull << c.q.bnum) - 1ull));
+  // rings where this wave already holds a claim were tried above
+  const uint32_t pend_r = __shfl(c.pend, (int)r);
+  const uint64_t busy = ballot(in && pend_r != kInf);
+  uint64_t mw = m & ~busy & (c.q.bnum >= 64 ? ~0ull : ((1ull << c.q.bnum) - 1ull));
   while (mw) {
     const uint32_t j = first_lane(mw);
     mw &= mw - 1;
