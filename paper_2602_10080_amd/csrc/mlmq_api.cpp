@@ -676,21 +676,40 @@ const mlmq_config* resolve_config(const mlmq_graph* g, const mlmq_config* cfg, m
 // mesh/road-like graphs keep a FIFO L2 with local L0/L1 queues; skewed
 // power-law graphs get buckets and the grid-wide hub tier.
 void heuristic_config(const mlmq_graph* g, mlmq_config* c) {
+  // Feature-driven defaults (Section 3.5, Table 2 features), set from
+  // measurements on the synthetic stand-ins of the paper's graph classes.
   const mlmq_features& f = g->features;
   const uint32_t mean_w = (uint32_t)std::max(1.0, f.avg_w);
-  c->delta1 = std::max<uint32_t>(1, mean_w * 2);
   c->delta2_log2 = log2_ceil(std::max<uint32_t>(1, mean_w));
+  uint32_t num = 1, den = 1;  // share of the resident waves to launch
   if (f.max_deg > 64 && f.std_deg > f.avg_deg) {
+    // power-law: near-far L1 with a narrow window over a FIFO L2, hub chunks
+    // for the top vertices, two thirds of the resident waves (less contention)
     c->l0_rows = 1;
-    c->l1_type = MLMQ_L1_VEC;
+    c->l1_type = MLMQ_L1_NEARFAR;
     c->l2_type = MLMQ_L2_FIFO;
+    c->delta1 = std::max<uint32_t>(1, mean_w / 2);
     c->th_hub = 8192;
+    c->hub_chunk = 4096;
+    num = 2;
+    den = 3;
   } else {
-    c->l0_rows = 2;
-    c->l1_type = MLMQ_L1_VEC;
+    // low, even degree (meshes, road-like grids): no L0 (it would follow
+    // private chains ahead of the frontier), near-far L1 two mean weights
+    // wide, FIFO L2 with donations, two ninths of the resident waves
+    c->l0_rows = 0;
+    c->l1_type = MLMQ_L1_NEARFAR;
     c->l2_type = MLMQ_L2_FIFO;
+    c->delta1 = std::max<uint32_t>(1, mean_w * 2);
     c->th_hub = 0;
+    num = 2;
+    den = 9;
   }
+  LaunchShape s;
+  if (num != den && launch_shape(*c, c->l1_cap, c->l1_type == MLMQ_L1_NEARFAR, &s) == MLMQ_OK)
+    c->grid_wgs = std::max<uint32_t>(64, s.max_grid * num / den);
+  else
+    (void)hipGetLastError();
 }
 
 // One solve attempt sequence (with capacity retries) on a slab.

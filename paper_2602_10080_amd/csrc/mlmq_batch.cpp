@@ -204,44 +204,43 @@ std::vector<mlmq_config> candidates(const mlmq_graph* g) {
   const mlmq_features& f = g->features;
   const bool skewed = f.max_deg > 64 && f.std_deg > f.avg_deg;
   const uint32_t mw = (uint32_t)std::max(1.0, f.avg_w);
+  uint32_t l2mw = 0;
+  while ((2u << l2mw) <= mw) ++l2mw;
   std::vector<mlmq_config> out;
-  auto add = [&](uint8_t l0, uint8_t l1, uint8_t l2, uint32_t d1, uint32_t d2l, uint32_t wb, uint32_t wg,
-                 uint32_t grid_div) {
+  // share = num / 9 of the resident waves (9 = all)
+  auto add = [&](uint8_t l0, uint8_t l1, uint8_t l2, uint32_t d1, uint32_t d2l, uint32_t num9) {
     mlmq_config c = base;
     c.l0_rows = l0;
     c.l1_type = l1;
     c.l2_type = l2;
-    c.delta1 = d1;
+    c.delta1 = std::max<uint32_t>(1, d1);
     c.delta2_log2 = d2l;
-    c.l1_flush_wb = wb;
-    c.wg_size = wg;
     c.grid_wgs = 0;
-    if (grid_div > 1) {
+    if (num9 < 9) {
       LaunchShape s;
       if (launch_shape(c, l1 == MLMQ_L1_NONE ? 64u : c.l1_cap, l1 == MLMQ_L1_NEARFAR, &s) == MLMQ_OK)
-        c.grid_wgs = std::max<uint32_t>(1, s.max_grid / grid_div);
+        c.grid_wgs = std::max<uint32_t>(64, s.max_grid * num9 / 9);
+      else
+        (void)hipGetLastError();
     }
     out.push_back(c);
   };
-  uint32_t l2mw = 0;
-  while ((2u << l2mw) <= mw) ++l2mw;
-  add(base.l0_rows, base.l1_type, base.l2_type, base.delta1, base.delta2_log2, base.l1_flush_wb, 64, 1);
-  for (uint8_t l0 : {0, 1, 2, 4}) add(l0, MLMQ_L1_VEC, MLMQ_L2_FIFO, 2 * mw, l2mw, 64, 64, 1);
-  add(2, MLMQ_L1_NONE, MLMQ_L2_FIFO, 2 * mw, l2mw, 0, 64, 1);
-  for (uint32_t d1 : {mw, 4 * mw}) {
-    add(1, MLMQ_L1_NEARFAR, MLMQ_L2_FIFO, d1, l2mw, 0, 64, 1);
-    add(1, MLMQ_L1_FILTER, MLMQ_L2_FIFO, d1, l2mw, 0, 64, 1);
-  }
-  for (uint32_t d2 : {l2mw, l2mw + 2}) {
-    add(1, MLMQ_L1_VEC, MLMQ_L2_BUCKET, 2 * mw, d2, 64, 64, 1);
-    add(1, MLMQ_L1_NEARFAR, MLMQ_L2_BUCKET, 2 * mw, d2, 0, 64, 1);
-  }
-  for (uint32_t div : {2u, 4u, 8u}) add(base.l0_rows, base.l1_type, base.l2_type, base.delta1, base.delta2_log2,
-                                        base.l1_flush_wb, 64, div);
+  out.push_back(base);
   if (skewed) {
-    for (auto& c : out) c.th_hub = 8192;
+    for (uint32_t share : {4u, 6u, 9u}) {
+      add(1, MLMQ_L1_NEARFAR, MLMQ_L2_FIFO, mw / 2, l2mw, share);
+      add(1, MLMQ_L1_VEC, MLMQ_L2_FIFO, mw, l2mw, share);
+    }
+    add(2, MLMQ_L1_NEARFAR, MLMQ_L2_FIFO, mw / 4, l2mw, 6);
+    add(1, MLMQ_L1_NEARFAR, MLMQ_L2_FIFO, mw / 8, l2mw, 6);
+    add(1, MLMQ_L1_NEARFAR, MLMQ_L2_BUCKET, mw / 4, l2mw > 0 ? l2mw - 1 : 0, 6);
   } else {
-    for (auto& c : out) c.th_hub = 0;
+    for (uint32_t share : {1u, 2u, 3u, 6u}) {
+      add(0, MLMQ_L1_NEARFAR, MLMQ_L2_FIFO, 2 * mw, l2mw, share);
+      add(0, MLMQ_L1_NEARFAR, MLMQ_L2_BUCKET, mw, l2mw + 2, share);
+    }
+    add(0, MLMQ_L1_NEARFAR, MLMQ_L2_FIFO, mw, l2mw, 2);
+    add(0, MLMQ_L1_NEARFAR, MLMQ_L2_BUCKET, 2 * mw, l2mw + 3, 3);
   }
   return out;
 }
@@ -292,6 +291,9 @@ extern "C" int mlmq_autotune(mlmq_graph* g, uint32_t budget_ms, mlmq_config* out
     st.struct_size = sizeof(st);
     c.stats_out = &st;
     c.stream = out ? out->stream : nullptr;
+    // a poor candidate may not take more than the whole budget
+    c.timeout_ms = std::min<uint32_t>(c.timeout_ms ? c.timeout_ms : 60000, std::max<uint32_t>(200, budget_ms));
+    c.max_retries = 1;
     double total = 0;
     bool okc = true;
     for (uint32_t s : srcs) {
