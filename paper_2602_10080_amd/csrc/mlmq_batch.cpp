@@ -18,6 +18,9 @@ using namespace mlmq;
 
 namespace {
 
+// Fewest waves a batched query is given when the batch is wide.
+constexpr uint32_t kBatchShare = 64;
+
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 uint64_t mix(uint64_t h, uint64_t x) {
@@ -60,8 +63,10 @@ extern "C" int mlmq_sssp_batch(const mlmq_graph* const* graphs, const uint32_t* 
     rc = check_config(&conf[i]);
     if (rc) return rc;
   }
-  // Launch shape from the first config; LDS sized for the largest L1.
+  // Launch shape from the first config, but always the whole device: the
+  // queries share it. LDS is sized for the largest L1.
   mlmq_config lc = conf[0];
+  lc.grid_wgs = 0;
   uint32_t l1cap = 64;
   bool two = false;
   for (auto& c : conf) {
@@ -76,7 +81,11 @@ extern "C" int mlmq_sssp_batch(const mlmq_graph* const* graphs, const uint32_t* 
   std::vector<int32_t> order((size_t)nq);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return graphs[a]->m > graphs[b]->m; });
-  const uint32_t conc = (uint32_t)std::min<int32_t>(nq, 16);
+  // Queries in flight at once: each gets an equal share of the resident
+  // waves (at least kBatchShare), capped by its own tuned launch size. A
+  // single solve is latency-bound long before it fills the device, so many
+  // narrow queries finish more work per second than a few wide ones.
+  const uint32_t conc = (uint32_t)std::max<int64_t>(1, std::min<int64_t>(nq, shape.grid / kBatchShare));
   std::vector<QueryPlan> plans((size_t)nq);
   size_t bytes = 0;
   uint32_t init_words = 1;
@@ -105,7 +114,8 @@ extern "C" int mlmq_sssp_batch(const mlmq_graph* const* graphs, const uint32_t* 
   for (int32_t k = 0; k < nq; ++k) {
     const int32_t i = order[k];
     const mlmq_config& c = conf[i];
-    const uint32_t want = c.grid_wgs ? std::min(c.grid_wgs, shape.grid) : std::max<uint32_t>(4, shape.grid / conc);
+    const uint32_t share = std::max<uint32_t>(4, shape.grid / conc);
+    const uint32_t want = c.grid_wgs ? std::min(c.grid_wgs, share) : share;
     h_desc[k] = make_desc(graphs[i], c, plans[k], base + off, dist_outs[i], sources[i], want);
     off = align_up(off + plans[k].bytes, 256);
   }
