@@ -19,7 +19,7 @@ using namespace mlmq;
 namespace {
 
 // Fewest waves a batched query is given when the batch is wide.
-constexpr uint32_t kBatchShare = 64;
+constexpr uint32_t kBatchShare = 128;
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 

@@ -36,6 +36,9 @@ namespace {
 
 constexpr uint64_t kSlotClosedBit = 1ull << 31;
 constexpr size_t kMaxPending = 1u << 20;
+// Fewest waves a query gets while the server is busy (a single solve is
+// latency-bound well before it fills the device).
+constexpr uint32_t kMinShare = 128;
 
 uint64_t now_ns() {
   return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
@@ -246,7 +249,11 @@ bool admit(mlmq_server* s, std::string* err) {
     s->pending.pop_front();
     Slot& sl = s->slots[free_i];
     const mlmq_graph* g = s->graphs[r.graph];
-    const uint32_t want = s->want[r.graph];
+    // Wave share: the graph's own launch size when the server is quiet, an
+    // equal split of the resident waves (at least kMinShare) when it is busy.
+    uint32_t busy = 1 + (uint32_t)std::min<size_t>(s->pending.size(), 64);
+    for (const Slot& o : s->slots) busy += o.phase == Phase::kRun ? 1u : 0u;
+    const uint32_t want = std::max(std::min(s->want[r.graph], s->grid / busy), std::min(kMinShare, s->want[r.graph]));
     const QueryDesc d = make_desc(g, s->cfgs[r.graph], plan, s->d_pool + off, r.dist, r.source, want);
     const uint32_t gen = s->next_gen++;
     if (s->next_gen == 0) s->next_gen = 1;
@@ -373,10 +380,8 @@ int mlmq_server_create(const mlmq_graph* const* graphs, int32_t ngraphs, uint64_
   s->grid = (uint32_t)per_cu * (uint32_t)di->cus;
   if (cfg && cfg->grid_wgs) s->grid = std::min(s->grid, cfg->grid_wgs);
   for (int32_t i = 0; i < ngraphs; ++i) {
-    // a query gets a share of the resident waves that grows with its size
-    const double m = (double)graphs[i]->m;
-    uint32_t w = (uint32_t)std::min<double>(s->grid, std::max(32.0, m / 32768.0));
-    if (s->cfgs[i].grid_wgs) w = std::min(s->grid, s->cfgs[i].grid_wgs);
+    // at most the graph's own launch size (its config's grid_wgs, else all)
+    uint32_t w = s->cfgs[i].grid_wgs ? std::min(s->grid, s->cfgs[i].grid_wgs) : s->grid;
     s->want.push_back(std::min<uint32_t>(std::max<uint32_t>(w, 1), 0x7FFF));
   }
 
