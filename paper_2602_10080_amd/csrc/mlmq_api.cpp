@@ -468,14 +468,15 @@ void pool_trim() {
 
 // Launch shape for a config: workgroup size, LDS bytes and the number of
 // persistent workgroups that fit on the device at once.
-int launch_shape(const mlmq_config& c, uint32_t l1_cap, bool two, LaunchShape* out) {
+int launch_shape(const mlmq_config& c, uint32_t l1_cap, bool two, bool stage, LaunchShape* out) {
   const DeviceInfo* di = device_info();
   LaunchShape s;
   s.wg = c.wg_size;
   s.waves = c.wg_size / 64;
   s.l1_cap = l1_cap;
   s.two = two;
-  s.lds = worker_lds_bytes(s.waves, l1_cap, two);
+  s.stage = stage;
+  s.lds = worker_lds_bytes(s.waves, l1_cap, two, stage);
   if (s.lds > di->lds_per_wg)
     return set_error(MLMQ_ERR_INVALID_ARG, "L1 needs %zu bytes of LDS per workgroup (limit %zu)", s.lds,
                      di->lds_per_wg);
@@ -499,6 +500,7 @@ LaunchArgs make_args(const QueryDesc* d_desc, BatchCtrl* d_batch, int nq, const 
   a.nq = nq;
   a.l1_cap = s.l1_cap;
   a.l1_two = s.two ? 1u : 0u;
+  a.stage = s.stage ? 1u : 0u;
   a.waves = s.waves;
   a.timeout_ticks = (uint64_t)(timeout_ms ? timeout_ms : 60000) * di->ticks_per_ms;
   a.cap_wait_ticks = 20ull * di->ticks_per_ms;
@@ -706,7 +708,8 @@ void heuristic_config(const mlmq_graph* g, mlmq_config* c) {
     den = 9;
   }
   LaunchShape s;
-  if (num != den && launch_shape(*c, c->l1_cap, c->l1_type == MLMQ_L1_NEARFAR, &s) == MLMQ_OK)
+  if (num != den && launch_shape(*c, c->l1_cap, c->l1_type == MLMQ_L1_NEARFAR, c->l2_type == MLMQ_L2_BUCKET, &s) ==
+                        MLMQ_OK)
     c->grid_wgs = std::max<uint32_t>(64, s.max_grid * num / den);
   else
     (void)hipGetLastError();
@@ -719,7 +722,8 @@ int run_single(const mlmq_graph* g, uint32_t source, uint32_t* dist_out, const m
   hipStream_t stream = reinterpret_cast<hipStream_t>(c.stream);
   const bool dev_out = is_device_ptr(dist_out);
   LaunchShape shape;
-  rc = launch_shape(c, c.l1_type == MLMQ_L1_NONE ? 64u : c.l1_cap, c.l1_type == MLMQ_L1_NEARFAR, &shape);
+  rc = launch_shape(c, c.l1_type == MLMQ_L1_NONE ? 64u : c.l1_cap, c.l1_type == MLMQ_L1_NEARFAR,
+                    c.l2_type == MLMQ_L2_BUCKET, &shape);
   if (rc) return rc;
   uint32_t extra = 0, hub_scale = 1, retries = 0;
   for (;;) {

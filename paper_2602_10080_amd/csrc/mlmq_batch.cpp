@@ -68,13 +68,14 @@ extern "C" int mlmq_sssp_batch(const mlmq_graph* const* graphs, const uint32_t* 
   mlmq_config lc = conf[0];
   lc.grid_wgs = 0;
   uint32_t l1cap = 64;
-  bool two = false;
+  bool two = false, stage = false;
   for (auto& c : conf) {
     if (c.l1_type != MLMQ_L1_NONE) l1cap = std::max(l1cap, c.l1_cap);
     two = two || c.l1_type == MLMQ_L1_NEARFAR;
+    stage = stage || c.l2_type == MLMQ_L2_BUCKET;
   }
   LaunchShape shape;
-  rc = launch_shape(lc, l1cap, two, &shape);
+  rc = launch_shape(lc, l1cap, two, stage, &shape);
   if (rc) return rc;
   hipStream_t stream = lc.stream ? reinterpret_cast<hipStream_t>(lc.stream) : internal_stream();
   // Largest queries first, so the long ones start early (LPT order).
@@ -228,7 +229,8 @@ std::vector<mlmq_config> candidates(const mlmq_graph* g) {
     c.grid_wgs = 0;
     if (num9 < 9) {
       LaunchShape s;
-      if (launch_shape(c, l1 == MLMQ_L1_NONE ? 64u : c.l1_cap, l1 == MLMQ_L1_NEARFAR, &s) == MLMQ_OK)
+      if (launch_shape(c, l1 == MLMQ_L1_NONE ? 64u : c.l1_cap, l1 == MLMQ_L1_NEARFAR, l2 == MLMQ_L2_BUCKET, &s) ==
+          MLMQ_OK)
         c.grid_wgs = std::max<uint32_t>(64, s.max_grid * num9 / 9);
       else
         (void)hipGetLastError();

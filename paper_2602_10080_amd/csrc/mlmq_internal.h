@@ -11,6 +11,7 @@ constexpr int kWave = 64;               // CDNA wavefront width
 constexpr uint32_t kInf = 0xFFFFFFFFu;  // unreachable / "no ticket"
 constexpr int kMaxBuckets = 64;         // L2 buckets: one per lane of a scanning wave
 constexpr int kMaxL0Rows = 4;           // L0 register rows of 64 elements
+constexpr uint32_t kStageB = 8;         // buckets after the head with a write-combining row
 
 // Device status word of a query (ctrl->error).
 enum : uint32_t {
@@ -115,6 +116,7 @@ struct LaunchArgs {
   int32_t nq;
   uint32_t l1_cap;     // LDS ring capacity this launch was sized for
   uint32_t l1_two;     // 1 if a second (far) ring is allocated
+  uint32_t stage;      // 1 if the bucket-queue write-combining area is allocated
   uint32_t waves;      // waves per workgroup (always 1)
   uint64_t timeout_ticks;   // device watchdog (wall-clock ticks)
   uint64_t cap_wait_ticks;  // longest wait for a free L2 slot before overflow
@@ -134,6 +136,8 @@ struct ServerArgs {
   ServerCtrl* ctl;
   int32_t nslots;          // <= 64
   uint32_t l1_cap;         // LDS ring capacity the launch was sized for
+  uint32_t l1_two;         // 1 if a second (far) ring is allocated
+  uint32_t stage;          // 1 if the bucket-queue write-combining area is allocated
   uint64_t timeout_ticks;  // per-query device watchdog from the moment a wave joins
   uint64_t cap_wait_ticks;
   uint64_t idle_exit_ticks;  // a wave with no work for this long leaves the kernel
@@ -159,7 +163,7 @@ struct QueryResult {
 };
 
 // Bytes of dynamic LDS a workgroup needs.
-size_t worker_lds_bytes(uint32_t waves, uint32_t l1_cap, bool two_rings);
+size_t worker_lds_bytes(uint32_t waves, uint32_t l1_cap, bool two_rings, bool stage);
 
 // Kernel launchers (defined in mlmq_kernels.hip).
 hipError_t launch_init(const QueryDesc* d_queries, BatchCtrl* d_batch, int nq, uint32_t max_words, hipStream_t s);

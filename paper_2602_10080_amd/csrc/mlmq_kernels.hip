@@ -123,6 +123,9 @@ struct Ctx {
   uint64_t* stg;  // 64-entry staging row (LDS)
   uint64_t* l1;   // L1 main (or near) ring (LDS)
   uint64_t* far;  // L1 far ring (LDS, near-far only)
+  uint64_t* stage;  // bucket write-combining rows, kStageB x 64 (LDS, bucket L2 only)
+  uint32_t sb;      // lane s < kStageB: absolute bucket held in row s (kInf = none)
+  uint32_t sn;      // lane s < kStageB: elements in row s
   uint32_t l1mask;
   uint32_t qh, qt, fh, ft;   // L1 ring counters (monotonic)
   uint32_t thresh;           // NF (near-far) or F (filter)
@@ -269,21 +272,18 @@ __device__ __forceinline__ bool l2_put_block(Ctx& c, uint32_t ring, uint64_t e, 
   return true;
 }
 
-// L2 Write of a lane vector. Bucket queue (Section 4.2, L2DQ): bucket index
-// floor(d / Delta) relative to the head bucket, clamped into [0, bmax - 1];
-// one block per distinct bucket present in the vector.
-__device__ __forceinline__ void l2_write(Ctx& c, uint64_t e, bool ok) {
-  uint64_t m = ballot(ok);
-  if (!m) return;
-  if (c.q.nrings == 1) {
-    l2_put_block(c, 0, e, ok, m);
-    return;
-  }
+// Ring of absolute bucket b seen from head bucket cur: bucket index relative
+// to the head, clamped into [0, bmax - 1] (Section 4.2, L2DQ).
+__device__ __forceinline__ uint32_t bucket_ring(const Ctx& c, uint32_t cur, uint32_t b) {
   const uint32_t nr = c.q.nrings;
-  const uint32_t cur = uni(ld32(&c.q.ctrl->cur.v));
-  const uint32_t b = elem_d(e) >> c.q.d2_log2;
   const uint32_t rel = b <= cur ? 0u : min(b - cur, nr - 1u);
-  const uint32_t ring = (cur + rel) & (nr - 1u);
+  return (cur + rel) & (nr - 1u);
+}
+
+// Writes a vector to the bucket rings, one block per bucket present in it.
+__device__ __forceinline__ void l2_write_direct(Ctx& c, uint32_t cur, uint64_t e, bool ok) {
+  const uint32_t ring = bucket_ring(c, cur, elem_d(e) >> c.q.d2_log2);
+  uint64_t m = ballot(ok);
   while (m) {
     const uint32_t r0 = lane_val(ring, first_lane(m));
     const bool sel = ok && ring == r0;
@@ -291,6 +291,81 @@ __device__ __forceinline__ void l2_write(Ctx& c, uint64_t e, bool ok) {
     if (!l2_put_block(c, r0, e, sel, ms)) return;
     ok = ok && !sel;
     m &= ~ms;
+  }
+}
+
+// Write combining for the bucket queue: elements of the kStageB buckets after
+// the head gather in one LDS row per bucket and go out as full 64-element
+// blocks; the head bucket and farther buckets go out at once. A wave empties
+// its rows whenever its L0 and L1 are empty, before it can count itself idle,
+// so delayed-count termination still sees every element.
+__device__ __forceinline__ void stage_flush_row(Ctx& c, uint32_t s, uint32_t cur) {
+  const uint32_t n = lane_val(c.sn, s);
+  const uint32_t b = lane_val(c.sb, s);
+  if (n) {
+    const bool ok = lane() < n;
+    const uint64_t x = ok ? c.stage[s * 64u + lane()] : 0;
+    compiler_fence();
+    l2_put_block(c, bucket_ring(c, cur, b), x, ok, ballot(ok));
+  }
+  if (lane() == s) {
+    c.sn = 0;
+    c.sb = kInf;
+  }
+}
+
+__device__ __forceinline__ void stage_flush_all(Ctx& c) {
+  const uint64_t m = ballot(lane() < kStageB && c.sn != 0);
+  if (!m) return;
+  const uint32_t cur = uni(ld32(&c.q.ctrl->cur.v));
+  for (uint64_t x = m; x && !c.stop; x &= x - 1) stage_flush_row(c, first_lane(x), cur);
+}
+
+// L2 Write of a lane vector.
+__device__ __forceinline__ void l2_write(Ctx& c, uint64_t e, bool ok) {
+  if (!ballot(ok)) return;
+  if (c.q.nrings == 1) {
+    l2_put_block(c, 0, e, ok, ballot(ok));
+    return;
+  }
+  const uint32_t cur = uni(ld32(&c.q.ctrl->cur.v));
+  const uint32_t b = elem_d(e) >> c.q.d2_log2;
+  const uint32_t window = min(kStageB, c.q.nrings - 1u);
+  const bool st = c.stage != nullptr && ok && b > cur && b - cur <= window;
+  const bool direct = ok && !st;
+  if (ballot(direct)) l2_write_direct(c, cur, e, direct);
+  // the window's buckets are consecutive, so each maps to its own row
+  const uint32_t slot = b & (kStageB - 1u);
+  uint64_t msk = ballot(st);
+  while (msk && !c.stop) {
+    const uint32_t f = first_lane(msk);
+    const uint32_t s = lane_val(slot, f);
+    const uint32_t bs = lane_val(b, f);
+    const bool sel = st && slot == s;
+    const uint64_t ms = ballot(sel);
+    msk &= ~ms;
+    if (lane_val(c.sb, s) != bs) {
+      stage_flush_row(c, s, cur);  // the row held an older bucket
+      if (lane() == s) c.sb = bs;
+    }
+    uint32_t cnt = lane_val(c.sn, s);
+    const uint32_t k = popc(ms);
+    const uint32_t r = rank_of(ms);
+    const uint32_t room = 64u - cnt;
+    if (sel && r < room) c.stage[s * 64u + cnt + r] = e;
+    compiler_fence();
+    if (k >= room) {
+      // the row is full: it goes out as one block, the rest starts it anew
+      if (lane() == s) c.sn = 64u;
+      stage_flush_row(c, s, cur);
+      if (lane() == s) c.sb = bs;
+      if (sel && r >= room) c.stage[s * 64u + (r - room)] = e;
+      compiler_fence();
+      cnt = k - room;
+    } else {
+      cnt += k;
+    }
+    if (lane() == s) c.sn = cnt;
   }
 }
 
@@ -411,7 +486,7 @@ __device__ __forceinline__ bool l2_read(Ctx& c, uint64_t& e, bool& ok) {
   // the grid run ahead of the frontier. A wave that has found nothing for a
   // while moves it anyway, which bounds the wait when local queues stay busy.
   if (m && !(m & 1u)) {
-    bool go = c.idle >= 32u;
+    bool go = c.idle >= 8u;
     if (!go) {
       const uint32_t hungry = uni(ld32(&c.q.ctrl->hungry.v));
       const uint32_t act = uni(ld32(&c.q.ctrl->active.v));
@@ -841,6 +916,7 @@ __device__ __forceinline__ void run_query(Ctx& c) {
       got = l1_take(c, e, ok);
       c.ct[kCtL1Reads] += 1;
     } else {
+      if (c.stage) stage_flush_all(c);
       uint32_t hv, hd, heb, hee;
       beat(c.beat, kPtHub, c.it);
       if (hub_claim(c, hv, hd, heb, hee)) {
@@ -910,12 +986,15 @@ __device__ __forceinline__ uint32_t pick_query(const LaunchArgs& a) {
 // Fresh wave state for query q: empty L0 and L1 (the LDS rings need no
 // clearing, only their counters), no pending tickets, no counters.
 __device__ __forceinline__ void setup_ctx(Ctx& c, const QueryDesc& q, uint64_t* smem, uint32_t l1_cap_alloc,
-                                          const uint32_t* cancel, uint64_t deadline, uint64_t cap_wait,
-                                          uint32_t* beat_word) {
+                                          uint32_t two_alloc, uint32_t stage_alloc, const uint32_t* cancel,
+                                          uint64_t deadline, uint64_t cap_wait, uint32_t* beat_word) {
   c.q = q;
   c.stg = smem;
   c.l1 = smem + 64;
   c.far = c.l1 + l1_cap_alloc;
+  c.stage = (stage_alloc && q.nrings > 1) ? c.far + (two_alloc ? l1_cap_alloc : 0u) : nullptr;
+  c.sb = kInf;
+  c.sn = 0;
   c.l1mask = c.q.l1_cap - 1u;
   c.qh = c.qt = c.fh = c.ft = 0;
   c.thresh = c.q.l1_type == MLMQ_L1_FILTER ? c.q.delta1 : 0u;
@@ -998,7 +1077,8 @@ __global__ void __launch_bounds__(64) mlmq_worker(LaunchArgs a) {
     const uint32_t qi = pick_query(a);
     if (qi == kInf) break;
     Ctx c;
-    setup_ctx(c, a.queries[qi], smem, a.l1_cap, &a.batch->cancel.v, t0 + a.timeout_ticks, a.cap_wait_ticks, my_beat);
+    setup_ctx(c, a.queries[qi], smem, a.l1_cap, a.l1_two, a.stage, &a.batch->cancel.v, t0 + a.timeout_ticks,
+              a.cap_wait_ticks, my_beat);
     run_query(c);
     flush_counters(c);
     if (lane() == 0) add32(&c.q.ctrl->finished.v, 1u);
@@ -1034,8 +1114,8 @@ __global__ void __launch_bounds__(64) mlmq_server_worker(ServerArgs a) {
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       const QueryDesc q = load_desc_coherent(a.slots + s);
       Ctx c;
-      setup_ctx(c, q, smem, a.l1_cap, &a.ctl->cancel.v, (uint64_t)wall_clock64() + a.timeout_ticks, a.cap_wait_ticks,
-                nullptr);
+      setup_ctx(c, q, smem, a.l1_cap, a.l1_two, a.stage, &a.ctl->cancel.v, (uint64_t)wall_clock64() + a.timeout_ticks,
+                a.cap_wait_ticks, nullptr);
       run_query(c);
       flush_counters(c);
       if (l == 0) {
@@ -1149,9 +1229,9 @@ __global__ void mlmq_gather(const QueryDesc* qs, int nq, QueryResult* out) {
 
 // ------------------------------------------------------------ host launchers
 
-size_t worker_lds_bytes(uint32_t waves, uint32_t l1_cap, bool two_rings) {
+size_t worker_lds_bytes(uint32_t waves, uint32_t l1_cap, bool two_rings, bool stage) {
   (void)waves;
-  return 8ull * (64ull + (uint64_t)l1_cap * (two_rings ? 2u : 1u));
+  return 8ull * (64ull + (uint64_t)l1_cap * (two_rings ? 2u : 1u) + (stage ? 64ull * kStageB : 0ull));
 }
 
 hipError_t launch_init(const QueryDesc* d_queries, BatchCtrl* d_batch, int nq, uint32_t max_words, hipStream_t s) {

@@ -352,7 +352,7 @@ int mlmq_server_create(const mlmq_graph* const* graphs, int32_t ngraphs, uint64_
   s->nslots = max_slots;
   s->budget = mem_budget_bytes;
   uint32_t l1_alloc = 64;
-  bool two = false;
+  bool two = false, stage = false;
   uint32_t timeout_ms = 0;
   for (int32_t i = 0; i < ngraphs; ++i) {
     mlmq_config tmp;
@@ -364,6 +364,7 @@ int mlmq_server_create(const mlmq_graph* const* graphs, int32_t ngraphs, uint64_
     s->cfgs.push_back(cc);
     if (cc.l1_type != MLMQ_L1_NONE) l1_alloc = std::max(l1_alloc, cc.l1_cap);
     two |= cc.l1_type == MLMQ_L1_NEARFAR;
+    stage |= cc.l2_type == MLMQ_L2_BUCKET;
     timeout_ms = std::max(timeout_ms, cc.timeout_ms);
   }
   auto fail = [&](int code) {
@@ -371,7 +372,7 @@ int mlmq_server_create(const mlmq_graph* const* graphs, int32_t ngraphs, uint64_
     return code;
   };
   const DeviceInfo* di = device_info();
-  s->lds = worker_lds_bytes(1, l1_alloc, two);
+  s->lds = worker_lds_bytes(1, l1_alloc, two, stage);
   if (s->lds > di->lds_per_wg) return fail(set_error(MLMQ_ERR_INVALID_ARG, "L1 does not fit in LDS"));
   int per_cu = 0;
   hipError_t e = server_occupancy(s->lds, &per_cu);
@@ -425,6 +426,8 @@ int mlmq_server_create(const mlmq_graph* const* graphs, int32_t ngraphs, uint64_
   a.ctl = s->d_ctl;
   a.nslots = max_slots;
   a.l1_cap = l1_alloc;
+  a.l1_two = two ? 1u : 0u;
+  a.stage = stage ? 1u : 0u;
   s->timeout_ms = timeout_ms ? timeout_ms : 60000;
   a.timeout_ticks = (uint64_t)s->timeout_ms * di->ticks_per_ms;
   a.cap_wait_ticks = 20ull * di->ticks_per_ms;

@@ -104,7 +104,8 @@ extern "C" int sim_sssp(int32_t n, const int32_t* off, const int32_t* col, const
   const uint32_t waves = wg_size / 64;
   const uint32_t l1cap = q->l1_cap;
   const bool two = k[1] == MLMQ_L1_NEARFAR;
-  const size_t lds = worker_lds_bytes(waves, l1cap, two);
+  const bool stage = k[2] == 1;
+  const size_t lds = worker_lds_bytes(waves, l1cap, two, stage);
   LaunchArgs a;
   std::memset(&a, 0, sizeof(a));
   a.queries = q;
@@ -112,6 +113,7 @@ extern "C" int sim_sssp(int32_t n, const int32_t* off, const int32_t* col, const
   a.nq = 1;
   a.l1_cap = l1cap;
   a.l1_two = two;
+  a.stage = stage;
   a.waves = waves;
   a.timeout_ticks = (uint64_t)k[14] * 100000ull;
   a.cap_wait_ticks = 200ull * 100000ull;
@@ -198,7 +200,8 @@ extern "C" int sim_server(int32_t n, const int32_t* off, const int32_t* col, con
   ctl->cancel.v = 0;
   const uint32_t l1cap = k[1] == MLMQ_L1_NONE ? 64u : k[3];
   const bool two = k[1] == MLMQ_L1_NEARFAR;
-  const size_t lds = worker_lds_bytes(1, l1cap, two);
+  const bool stage = k[2] == 1;
+  const size_t lds = worker_lds_bytes(1, l1cap, two, stage);
   ServerArgs a;
   std::memset(&a, 0, sizeof(a));
   a.slots = slots;
@@ -207,6 +210,8 @@ extern "C" int sim_server(int32_t n, const int32_t* off, const int32_t* col, con
   a.ctl = ctl;
   a.nslots = nslots;
   a.l1_cap = l1cap;
+  a.l1_two = two;
+  a.stage = stage;
   a.timeout_ticks = (uint64_t)k[14] * 100000ull;
   a.cap_wait_ticks = 200ull * 100000ull;
   a.idle_exit_ticks = (uint64_t)k[14] * 100000ull;
