@@ -686,15 +686,21 @@ void heuristic_config(const mlmq_graph* g, mlmq_config* c) {
   uint32_t num = 1, den = 1;  // share of the resident waves to launch
   if (f.max_deg > 64 && f.std_deg > f.avg_deg) {
     // power-law: near-far L1 with a narrow window over a FIFO L2, hub chunks
-    // for the top vertices, two thirds of the resident waves (less contention)
+    // for the top vertices. A small L1 sends work to L2 early, where idle
+    // waves find it (a large one keeps long private chains, which makes small
+    // graphs latency-bound); the launch grows with the edge count up to six
+    // one-wave workgroups per CU.
     c->l0_rows = 1;
     c->l1_type = MLMQ_L1_NEARFAR;
     c->l2_type = MLMQ_L2_FIFO;
     c->delta1 = std::max<uint32_t>(1, mean_w / 2);
     c->th_hub = 8192;
     c->hub_chunk = 4096;
-    num = 2;
-    den = 3;
+    const double m = f.nnz;
+    c->l1_cap = m < 64e6 ? 128 : (m < 192e6 ? 256 : 512);
+    const uint32_t cus = (uint32_t)std::max(1, device_info()->cus);
+    c->grid_wgs = (uint32_t)std::min<double>(6.0 * cus, std::max(512.0, m / 32768.0));
+    return;
   } else {
     // low, even degree (meshes, road-like grids): no L0 (it would follow
     // private chains ahead of the frontier), near-far L1 two mean weights

@@ -239,13 +239,25 @@ std::vector<mlmq_config> candidates(const mlmq_graph* g) {
   };
   out.push_back(base);
   if (skewed) {
-    for (uint32_t share : {4u, 6u, 9u}) {
-      add(1, MLMQ_L1_NEARFAR, MLMQ_L2_FIFO, mw / 2, l2mw, share);
-      add(1, MLMQ_L1_VEC, MLMQ_L2_FIFO, mw, l2mw, share);
-    }
-    add(2, MLMQ_L1_NEARFAR, MLMQ_L2_FIFO, mw / 4, l2mw, 6);
-    add(1, MLMQ_L1_NEARFAR, MLMQ_L2_FIFO, mw / 8, l2mw, 6);
-    add(1, MLMQ_L1_NEARFAR, MLMQ_L2_BUCKET, mw / 4, l2mw > 0 ? l2mw - 1 : 0, 6);
+    // L1 capacity x launch size around the feature-driven default, then the
+    // other queue families at the default size
+    const uint32_t g0 = base.grid_wgs ? base.grid_wgs : 1024;
+    for (uint32_t cap : {128u, 256u, 512u})
+      for (uint32_t g : {g0 / 2, g0, g0 + g0 / 2}) {
+        mlmq_config c = base;
+        c.l1_cap = cap;
+        c.grid_wgs = std::max<uint32_t>(64, g);
+        out.push_back(c);
+      }
+    mlmq_config v = base;
+    v.l1_type = MLMQ_L1_VEC;
+    v.l1_flush_wb = 8;
+    out.push_back(v);
+    mlmq_config dq = base;
+    dq.l2_type = MLMQ_L2_BUCKET;
+    dq.delta2_log2 = l2mw > 0 ? l2mw - 1 : 0;
+    dq.delta1 = std::max<uint32_t>(1, mw / 4);
+    out.push_back(dq);
   } else {
     for (uint32_t share : {1u, 2u, 3u, 6u}) {
       add(0, MLMQ_L1_NEARFAR, MLMQ_L2_FIFO, 2 * mw, l2mw, share);
