@@ -59,3 +59,45 @@ def test_uniform_4m_wide_weights_sampled_sources():
     csr = gg.uniform(1 << 22, 1 << 25, wmax=65535, seed=15)
     for s in gg.sample_sources(csr, 2, seed=3):
         _solve_and_check("uniform4M", csr, int(s))
+
+
+def test_batch_rmat20_grid1024_autotuned():
+    """The batched form on the batch workload's graphs, autotuned configs:
+    every query equals the oracle."""
+    mlmq = _mlmq()
+    rmat = gg.rmat(20, 16, seed=1)
+    grid = gg.grid(1024, 1024, 0.05, seed=1)
+    gr, gd = mlmq.Graph.from_csr(rmat), mlmq.Graph.from_csr(grid)
+    cr, cd = mlmq.autotune(gr, 1000), mlmq.autotune(gd, 1000)
+    srcs = [int(x) for x in gg.sample_sources(rmat, 8, seed=2)] + [int(x) for x in gg.sample_sources(grid, 8, seed=3)]
+    graphs = [gr] * 8 + [gd] * 8
+    csrs = [rmat] * 8 + [grid] * 8
+    _say(f"[full] batch of {len(srcs)} queries, tuned {cr.as_dict()} / {cd.as_dict()}")
+    outs, status = mlmq.sssp_batch(graphs, srcs, configs=[cr] * 8 + [cd] * 8)
+    torch.cuda.synchronize()
+    assert status == [0] * 16
+    for c, s, o in zip(csrs, srcs, outs):
+        assert np.array_equal(mlmq.to_numpy(o), oracle.dijkstra(c, s)), s
+
+
+def test_serving_mix_on_serving_graphs():
+    """The serving form on the five serving graphs: a burst of requests,
+    all in flight together; each result equals the oracle."""
+    mlmq = _mlmq()
+    csrs = [gg.grid(512, 512, 0.05, seed=11), gg.grid(2048, 2048, 0.05, seed=12), gg.rmat(20, 16, seed=13),
+            gg.rmat(22, 16, seed=14), gg.uniform(1 << 22, 1 << 25, wmax=65535, seed=15)]
+    graphs = [mlmq.Graph.from_csr(c) for c in csrs]
+    rng = np.random.default_rng(21)
+    reqs = [(g, int(rng.integers(0, csrs[g].n))) for g in list(range(5)) * 2]
+    outs = [mlmq.new_dist(csrs[g].n) for g, _ in reqs]
+    torch.cuda.synchronize()
+    _say(f"[full] serving {len(reqs)} requests")
+    srv = mlmq.Server(graphs, mem_budget_bytes=8 << 30, max_slots=64)
+    try:
+        tickets = [srv.submit(g, s, o) for (g, s), o in zip(reqs, outs)]
+        status = [srv.wait(t, 60000) for t in tickets]
+    finally:
+        srv.close()
+    assert status == [0] * len(reqs)
+    for (g, s), o in zip(reqs, outs):
+        assert np.array_equal(mlmq.to_numpy(o), oracle.dijkstra(csrs[g], s)), (g, s)
