@@ -52,6 +52,10 @@ extern "C" {
 #define MLMQ_L1_NEARFAR 2 /* L1NF: near/far vectors split at NF, NF = min(far) + delta1 */
 #define MLMQ_L1_FILTER 3  /* L1FQ: keeps d <= F, the rest goes to L2; F = min(L2 batch) + delta1 */
 
+/* Relaxation (Section 4.1's relax step): label pre-check before atomicMin, or atomicMin alone */
+#define MLMQ_RELAX_PRECHECK 0
+#define MLMQ_RELAX_ATOMIC 1
+
 /* L2 (HBM) queue types, Section 4.2 and Table 1 */
 #define MLMQ_L2_FIFO 0   /* L2V: block-based lock-free FIFO ring */
 #define MLMQ_L2_BUCKET 1 /* L2DQ: bmax FIFO rings as buckets of width delta2 */
@@ -90,7 +94,9 @@ typedef struct mlmq_config {
   uint8_t l0_rows;   /* L0 capacity in 64-element rows per wave, 0..4 (0 = L0 off) */
   uint8_t l1_type;   /* MLMQ_L1_* */
   uint8_t l2_type;   /* MLMQ_L2_* */
-  uint8_t reserved0;
+  uint8_t relax_mode; /* MLMQ_RELAX_PRECHECK: read dist[v] first, atomicMin only if it may improve;
+                         MLMQ_RELAX_ATOMIC: atomicMin on every candidate (one memory round trip less
+                         on the critical path; for low-degree, latency-bound graphs) */
   uint32_t l1_cap;      /* L1 capacity per workgroup in elements (power of two, 64..8192) */
   uint32_t l1_flush_wb; /* L1V: flush all of L1 to L2 after every wb L1 writes (0 = never) */
   uint32_t delta1;      /* L1NF / L1FQ threshold step (distance units, >= 1) */

@@ -66,7 +66,7 @@ class Stats(ctypes.Structure):
 class Config(ctypes.Structure):
     _fields_ = [
         ("struct_size", ctypes.c_uint32), ("l0_rows", ctypes.c_uint8), ("l1_type", ctypes.c_uint8),
-        ("l2_type", ctypes.c_uint8), ("reserved0", ctypes.c_uint8), ("l1_cap", ctypes.c_uint32),
+        ("l2_type", ctypes.c_uint8), ("relax_mode", ctypes.c_uint8), ("l1_cap", ctypes.c_uint32),
         ("l1_flush_wb", ctypes.c_uint32), ("delta1", ctypes.c_uint32), ("delta2_log2", ctypes.c_uint32),
         ("bmax", ctypes.c_uint32), ("bnum", ctypes.c_uint32), ("th_v", ctypes.c_uint32),
         ("th_hub", ctypes.c_uint32), ("hub_chunk", ctypes.c_uint32), ("wg_size", ctypes.c_uint32),
@@ -75,7 +75,7 @@ class Config(ctypes.Structure):
         ("stats_out", ctypes.POINTER(Stats)),
     ]
 
-    KNOBS = ("l0_rows", "l1_type", "l2_type", "l1_cap", "l1_flush_wb", "delta1", "delta2_log2", "bmax",
+    KNOBS = ("l0_rows", "l1_type", "l2_type", "relax_mode", "l1_cap", "l1_flush_wb", "delta1", "delta2_log2", "bmax",
              "bnum", "th_v", "th_hub", "hub_chunk", "wg_size", "grid_wgs", "l2_capacity", "timeout_ms",
              "max_retries")
 

@@ -97,6 +97,8 @@ int check_config(const mlmq_config* c) {
   if (c->l0_rows > kMaxL0Rows) return set_error(MLMQ_ERR_INVALID_ARG, "l0_rows must be 0..%d", kMaxL0Rows);
   if (c->l1_type > MLMQ_L1_FILTER) return set_error(MLMQ_ERR_INVALID_ARG, "unknown l1_type %u", c->l1_type);
   if (c->l2_type > MLMQ_L2_BUCKET) return set_error(MLMQ_ERR_INVALID_ARG, "unknown l2_type %u", c->l2_type);
+  if (c->relax_mode > MLMQ_RELAX_ATOMIC)
+    return set_error(MLMQ_ERR_INVALID_ARG, "unknown relax_mode %u", c->relax_mode);
   if (c->l1_type != MLMQ_L1_NONE && (!is_pow2(c->l1_cap) || c->l1_cap < 64 || c->l1_cap > 8192))
     return set_error(MLMQ_ERR_INVALID_ARG, "l1_cap must be a power of two in [64, 8192]");
   if (c->delta1 < 1) return set_error(MLMQ_ERR_INVALID_ARG, "delta1 must be >= 1");
@@ -373,6 +375,7 @@ QueryDesc make_desc(const mlmq_graph* g, const mlmq_config& c, const QueryPlan& 
   d.th_hub = c.th_hub;
   d.hub_chunk = c.hub_chunk;
   d.want_wgs = want_wgs;
+  d.relax_mode = c.relax_mode;
   return d;
 }
 
@@ -704,8 +707,11 @@ void heuristic_config(const mlmq_graph* g, mlmq_config* c) {
   } else {
     // low, even degree (meshes, road-like grids): no L0 (it would follow
     // private chains ahead of the frontier), near-far L1 two mean weights
-    // wide, FIFO L2 with donations, two ninths of the resident waves
+    // wide, FIFO L2 with donations, two ninths of the resident waves, and
+    // atomicMin without the label pre-check (the solve is latency-bound: one
+    // round trip less per hop matters more than the extra atomics)
     c->l0_rows = 0;
+    c->relax_mode = MLMQ_RELAX_ATOMIC;
     c->l1_type = MLMQ_L1_NEARFAR;
     c->l2_type = MLMQ_L2_FIFO;
     c->delta1 = std::max<uint32_t>(1, mean_w * 2);

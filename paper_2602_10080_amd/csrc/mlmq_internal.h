@@ -101,7 +101,7 @@ struct QueryDesc {
   uint32_t th_hub;     // 0 = hub tier off
   uint32_t hub_chunk;
   uint32_t want_wgs;   // workgroups this query should get
-  uint32_t pad;
+  uint32_t relax_mode; // MLMQ_RELAX_*
 };
 
 // Batch-wide control (device memory).

@@ -721,8 +721,9 @@ constexpr int kRelaxUnroll = 4;
 
 // Relax U sub-batches of 64 edges (one edge per lane each; the relax step of
 // the paper's kernel sketch, with atomicMin): candidate nd = d + w
-// (saturating), a plain load of dist[v] filters hopeless candidates, then
-// atomicMin decides; a lane has new work iff nd < the previous label.
+// (saturating), a plain load of dist[v] filters hopeless candidates (unless
+// the query relaxes by atomicMin alone), then atomicMin decides; a lane has
+// new work iff nd < the previous label.
 // Lanes without an edge load entry 0 of adj / dist (both exist whenever
 // there is an edge to relax) so that every load is unconditional.
 template <int U>
@@ -745,7 +746,7 @@ __device__ __forceinline__ void relax_many(Ctx& c, const bool (&has)[U], const u
     v[u] = (uint32_t)a[u];
     nd[u] = (uint32_t)sum;
     const uint32_t lv = cand[u] ? v[u] : 0u;
-    lab[u] = ld_label(c.q.dist + lv);
+    lab[u] = c.q.relax_mode == MLMQ_RELAX_ATOMIC ? kInf : ld_label(c.q.dist + lv);
   }
   bool imp[U];
   uint32_t natom = 0;
