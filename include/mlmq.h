@@ -51,6 +51,8 @@ extern "C" {
 #define MLMQ_L1_VEC 1     /* L1V: FIFO vector, flushed to L2 after every l1_flush_wb writes */
 #define MLMQ_L1_NEARFAR 2 /* L1NF: near/far vectors split at NF, NF = min(far) + delta1 */
 #define MLMQ_L1_FILTER 3  /* L1FQ: keeps d <= F, the rest goes to L2; F = min(L2 batch) + delta1 */
+#define MLMQ_L1_SLF 4     /* L1SLF: deque; an item shorter than the head goes in front, others at the
+                             back (Small-Label-First); overflow goes to L2 */
 
 /* Relaxation (Section 4.1's relax step): label pre-check before atomicMin, or atomicMin alone */
 #define MLMQ_RELAX_PRECHECK 0

@@ -28,7 +28,8 @@ ERR_CANCELED = -7
 ERR_BUSY = -8
 UNREACHABLE = 0xFFFFFFFF
 
-L1_NONE, L1_VEC, L1_NEARFAR, L1_FILTER = 0, 1, 2, 3
+L1_NONE, L1_VEC, L1_NEARFAR, L1_FILTER, L1_SLF = 0, 1, 2, 3, 4
+RELAX_PRECHECK, RELAX_ATOMIC = 0, 1
 L2_FIFO, L2_BUCKET = 0, 1
 MEM_HOST, MEM_DEVICE = 0, 1
 

@@ -95,7 +95,7 @@ int check_config(const mlmq_config* c) {
   if (c->struct_size != sizeof(mlmq_config))
     return set_error(MLMQ_ERR_INVALID_ARG, "config struct_size %u != %zu", c->struct_size, sizeof(mlmq_config));
   if (c->l0_rows > kMaxL0Rows) return set_error(MLMQ_ERR_INVALID_ARG, "l0_rows must be 0..%d", kMaxL0Rows);
-  if (c->l1_type > MLMQ_L1_FILTER) return set_error(MLMQ_ERR_INVALID_ARG, "unknown l1_type %u", c->l1_type);
+  if (c->l1_type > MLMQ_L1_SLF) return set_error(MLMQ_ERR_INVALID_ARG, "unknown l1_type %u", c->l1_type);
   if (c->l2_type > MLMQ_L2_BUCKET) return set_error(MLMQ_ERR_INVALID_ARG, "unknown l2_type %u", c->l2_type);
   if (c->relax_mode > MLMQ_RELAX_ATOMIC)
     return set_error(MLMQ_ERR_INVALID_ARG, "unknown relax_mode %u", c->relax_mode);

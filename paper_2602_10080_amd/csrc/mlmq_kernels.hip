@@ -620,6 +620,28 @@ __device__ __forceinline__ bool l1_put(Ctx& c, uint64_t e, bool ok, bool& spill)
     c.ft += min(popc(mf), sf);
     return false;
   }
+  if (c.q.l1_type == MLMQ_L1_SLF) {
+    // Small-Label-First deque (Section 3.4): items shorter than the head go
+    // in front of it (read next), the others at the back.
+    const uint32_t hd = c.qt != c.qh ? elem_d(c.l1[c.qh & c.l1mask]) : kInf;
+    compiler_fence();
+    const bool fr = ok && d < hd;
+    const bool bk = ok && !fr;
+    const uint64_t mf = ballot(fr), mb = ballot(bk);
+    uint32_t space = cap - (c.qt - c.qh);
+    const uint32_t nf = min(popc(mf), space);
+    const uint32_t rf = rank_of(mf);
+    if (fr && rf < nf) c.l1[(c.qh - nf + rf) & c.l1mask] = e;
+    space -= nf;
+    const uint32_t nb = min(popc(mb), space);
+    const uint32_t rb = rank_of(mb);
+    if (bk && rb < nb) c.l1[(c.qt + rb) & c.l1mask] = e;
+    compiler_fence();
+    spill = (fr && rf >= nf) || (bk && rb >= nb);
+    c.qh -= nf;
+    c.qt += nb;
+    return false;
+  }
   bool keep = ok;
   spill = false;
   if (c.q.l1_type == MLMQ_L1_FILTER) {

@@ -42,6 +42,9 @@ CONFIGS = {
     "L0x2-L1NF-L2DQ-b64": dict(l0_rows=2, l1_type=2, l2_type=1, bmax=64, bnum=8, th_hub=0),
     "grid8-L1V-L2V": dict(l0_rows=2, l1_type=1, l2_type=0, grid_wgs=8, th_hub=0),
     "tinyL2-L1none": dict(l0_rows=0, l1_type=0, l2_type=0, l2_capacity=1024, th_hub=0),
+    "L0x1-L1SLF-L2V": dict(l0_rows=1, l1_type=4, l2_type=0, l1_cap=128, th_hub=0),
+    "L0x2-L1SLF-L2DQ-hub64": dict(l0_rows=2, l1_type=4, l2_type=1, bmax=16, bnum=2, delta2_log2=6, th_v=8, th_hub=64,
+                                  hub_chunk=64),
     "L0off-L1NF-L2V-atomic": dict(l0_rows=0, l1_type=2, l2_type=0, relax_mode=1, delta1=64, th_hub=0),
     "L0x1-L1FQ-L2DQ-atomic": dict(l0_rows=1, l1_type=3, l2_type=1, relax_mode=1, bmax=16, bnum=1, delta2_log2=6,
                                   delta1=64, th_hub=0),
