@@ -253,6 +253,11 @@ std::vector<mlmq_config> candidates(const mlmq_graph* g) {
     v.l1_type = MLMQ_L1_VEC;
     v.l1_flush_wb = 8;
     out.push_back(v);
+    mlmq_config slf = base;
+    slf.l1_type = MLMQ_L1_SLF;
+    out.push_back(slf);
+    slf.l0_rows = 2;
+    out.push_back(slf);
     mlmq_config dq = base;
     dq.l2_type = MLMQ_L2_BUCKET;
     dq.delta2_log2 = l2mw > 0 ? l2mw - 1 : 0;
