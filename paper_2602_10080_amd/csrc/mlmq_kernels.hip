@@ -793,11 +793,14 @@ __device__ __forceinline__ void relax_many(Ctx& c, const bool (&has)[U], const u
   for (int u = 0; u < U; ++u) emit(c, v[u], nd[u], imp[u]);
 }
 
-// Whole wave sweeps the edge range [eb, ee) of one vertex.
-__device__ __forceinline__ void process_range(Ctx& c, uint32_t d, uint32_t eb, uint32_t ee) {
+// Whole wave sweeps the edge range [eb, ee) of vertex v at distance d. Every
+// 1024 edges it looks at dist[v] again: once v has been improved, the rest of
+// the sweep is redundant (the improved item expands all of it anyway).
+__device__ __forceinline__ void process_range(Ctx& c, uint32_t v, uint32_t d, uint32_t eb, uint32_t ee) {
   constexpr int U = kRelaxUnroll;
   uint32_t x = eb;
   for (; x + 64u * U <= ee && !c.stop; x += 64u * U) {
+    if (x != eb && ((x - eb) & 1023u) == 0 && uni(ld_label(c.q.dist + v)) < d) break;
     bool has[U];
     uint32_t ed[U], dd[U];
 #pragma unroll
@@ -882,7 +885,7 @@ __device__ __forceinline__ void process_vec(Ctx& c, uint64_t e, bool ok) {
   while (mb && !c.stop) {
     const uint32_t j = first_lane(mb);
     mb &= mb - 1;
-    process_range(c, lane_val(d, j), lane_val(beg, j), lane_val(end, j));
+    process_range(c, lane_val(v, j), lane_val(d, j), lane_val(beg, j), lane_val(end, j));
   }
 }
 
@@ -948,7 +951,7 @@ __device__ __forceinline__ void run_query(Ctx& c) {
         refill_threshold(c, hd);
         c.ct[kCtHubChunks] += 1;
         c.idle = 0;
-        if (hd <= uni(ld_label(c.q.dist + hv))) process_range(c, hd, heb, hee);
+        if (hd <= uni(ld_label(c.q.dist + hv))) process_range(c, hv, hd, heb, hee);
         continue;
       }
       beat(c.beat, kPtL2Read, c.it);

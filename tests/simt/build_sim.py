@@ -24,7 +24,9 @@ def transformed_source(checked: bool = False) -> str:
         src = src.replace("c.q.dist + lv", "c.q.dist + simt_chk(lv, c.q.n, \"dist\", __LINE__)")
         src = src.replace("c.q.dist + v[u]", "c.q.dist + simt_chk(v[u], c.q.n, \"dist\", __LINE__)")
         src = src.replace("c.q.dist + hv", "c.q.dist + simt_chk(hv, c.q.n, \"dist\", __LINE__)")
-        for pat in ("c.q.adj[eidx]", "c.q.off[lv]", "c.q.dist + lv", "c.q.dist + v[u]", "c.q.dist + hv"):
+        src = src.replace("ld_label(c.q.dist + v)", "ld_label(c.q.dist + simt_chk(v, c.q.n, \"dist\", __LINE__))")
+        for pat in ("c.q.adj[eidx]", "c.q.off[lv]", "c.q.dist + lv", "c.q.dist + v[u]", "c.q.dist + hv",
+                    "ld_label(c.q.dist + v)"):
             assert pat in open(KERNEL).read(), pat
     src = src.replace("extern __shared__ uint64_t smem[];",
                       "uint64_t* smem = reinterpret_cast<uint64_t*>(simt::group->lds);")

@@ -61,7 +61,19 @@ GRAPHS = {
     "grid16": lambda: (gg.grid(16, 16, 0.0, seed=1), 0),
     "road24": lambda: (gg.grid(24, 20, 0.1, seed=2), 77),
     "rmat9": lambda: (lambda g: (g, gg.max_degree_vertex(g)))(gg.rmat(9, 8, seed=3)),
+    # two hubs of 1500 leaves, joined: long rows swept by one wave (re-checked every 1024 edges)
+    "hubs": lambda: (_hubs(), 0),
 }
+
+
+def _hubs():
+    rng = np.random.default_rng(7)
+    a = np.arange(2, 1502)
+    b = np.arange(1502, 3002)
+    src = np.concatenate([np.zeros(1500, int), a, np.ones(1500, int), b, [0, 1]] + [a[:700]])
+    dst = np.concatenate([a, np.zeros(1500, int), b, np.ones(1500, int), [1, 0]] + [b[:700]])
+    w = rng.integers(1, 256, src.size)
+    return gg.from_edges(3002, src, dst, w)
 
 
 @pytest.mark.parametrize("cfg", list(CFG))
