@@ -3,7 +3,8 @@
 TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the benchmark's
 CPU-baseline leg may use it; the GPU library never does, and the two share no
 code. See ``oracle.c`` for what each function computes and which passage of
-the paper it follows (Section 2.1: problem statement, Dijkstra, Bellman-Ford).
+the paper it follows (Section 2.1: problem statement, Dijkstra, Bellman-Ford;
+Section 5.7: breadth-first search).
 
 Every function here is pinned by tests against things other than itself:
 brute-force path enumeration, Floyd-Warshall, closed forms on grids, paths and
@@ -65,6 +66,8 @@ def _load():
         lib.oracle_certificate.argtypes = [i64, vp, vp, vp, i64, vp, i64p, i64p]
         lib.oracle_reach_stats.restype = ctypes.c_int
         lib.oracle_reach_stats.argtypes = [i64, vp, vp, i64p, i64p]
+        lib.oracle_bfs.restype = ctypes.c_int
+        lib.oracle_bfs.argtypes = [i64, vp, vp, i64, vp]
         _lib = lib
     return _lib
 
@@ -95,6 +98,16 @@ def dijkstra(g, src: int, allow_overflow: bool = False) -> np.ndarray:
 
 def bellman_ford(g, src: int, allow_overflow: bool = False) -> np.ndarray:
     return _solve("oracle_bellman_ford", g, src, allow_overflow)
+
+
+def bfs(g, src: int) -> np.ndarray:
+    """Breadth-first levels from src (fewest edges; UNREACHABLE where no path)."""
+    off, col, _ = _csr_args(g)
+    level = np.empty(g.n, dtype=np.uint32)
+    rc = _load().oracle_bfs(g.n, off.ctypes.data, col.ctypes.data, int(src), level.ctypes.data)
+    if rc != OK:
+        raise OracleError(rc, "oracle_bfs")
+    return level
 
 
 def certificate(g, src: int, dist: np.ndarray):

@@ -30,6 +30,9 @@
  *                        the shortest-distance vector (proof in the comment).
  *   oracle_reach_stats   n_reach / m_reach of a distance vector (edges counted
  *                        once per directed edge out of a reachable vertex).
+ *   oracle_bfs           breadth-first search levels (Section 5.7's BFS case
+ *                        study): the fewest edges on a path from s, by the
+ *                        textbook FIFO-queue traversal.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -276,5 +279,33 @@ int oracle_reach_stats(int64_t n, const int64_t* off, const uint32_t* D, int64_t
   }
   if (n_reach) *n_reach = nr;
   if (m_reach) *m_reach = mr;
+  return ORACLE_OK;
+}
+
+/* Breadth-first search: level[s] = 0; a vertex first reached from a vertex of
+ * level k gets level k + 1; vertices never reached keep UINT32_MAX. The FIFO
+ * queue visits vertices in non-decreasing level order, so the first time a
+ * vertex is reached is along a fewest-edge path. */
+int oracle_bfs(int64_t n, const int64_t* off, const int32_t* col, int64_t src, uint32_t* level) {
+  int rc = check_csr(n, off, col, src);
+  if (rc != ORACLE_OK) return rc;
+  if (!level) return ORACLE_ERR_INVALID_ARG;
+  int64_t* queue = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+  if (!queue) return ORACLE_ERR_OUT_OF_MEMORY;
+  for (int64_t v = 0; v < n; ++v) level[v] = INF32;
+  int64_t head = 0, tail = 0;
+  level[src] = 0;
+  queue[tail++] = src;
+  while (head < tail) {
+    const int64_t u = queue[head++];
+    for (int64_t e = off[u]; e < off[u + 1]; ++e) {
+      const int64_t v = col[e];
+      if (level[v] == INF32) {
+        level[v] = level[u] + 1;
+        queue[tail++] = v;
+      }
+    }
+  }
+  free(queue);
   return ORACLE_OK;
 }

@@ -284,3 +284,45 @@ def test_reach_stats():
     g = gg.from_edges(5, [0, 0, 1, 3, 3], [1, 2, 2, 4, 0], [1, 1, 1, 1, 1])
     d = oracle.dijkstra(g, 0)
     assert oracle.reach_stats(g, d) == (3, 3)
+
+
+# ---------------------------------------------------------------- BFS (Section 5.7)
+
+def test_bfs_grid_is_manhattan_distance():
+    """Closed form: on a full R x C grid, the fewest hops are |dr| + |dc|."""
+    R, C = 23, 31
+    g = gg.grid(R, C, 0.0, seed=4)
+    src = 7 * C + 11
+    lv = oracle.bfs(g, src)
+    r, c = np.divmod(np.arange(R * C), C)
+    assert np.array_equal(lv, np.abs(r - 7) + np.abs(c - 11))
+
+
+def test_bfs_path_and_unreachable():
+    n = 50
+    g = gg.from_edges(n, np.arange(n - 1), np.arange(1, n), np.full(n - 1, 200))
+    assert np.array_equal(oracle.bfs(g, 0), np.arange(n))
+    lv = oracle.bfs(g, 10)  # edges point forward only
+    assert (lv[:10] == oracle.UNREACHABLE).all() and np.array_equal(lv[10:], np.arange(n - 10))
+
+
+def test_bfs_equals_dijkstra_with_unit_weights():
+    """Independent reference: Dijkstra on the same graph with every weight 1."""
+    rng = np.random.default_rng(17)
+    for trial in range(60):
+        n = int(rng.integers(2, 40))
+        g = gg.random_small(n, int(rng.integers(0, 4 * n)), int(rng.integers(0, 2**31)), rng, wmin=0)
+        unit = gg.Csr(g.n, g.off, g.col, np.ones_like(g.w))
+        s = int(rng.integers(0, n))
+        assert np.array_equal(oracle.bfs(g, s), oracle.dijkstra(unit, s)), trial
+
+
+def test_bfs_matches_scipy_unweighted():
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.csgraph import shortest_path
+    g = gg.rmat(10, 8, seed=9)
+    s = gg.max_degree_vertex(g)
+    a = csr_matrix((np.ones(g.m), g.col, g.off), shape=(g.n, g.n))
+    ref = shortest_path(a, unweighted=True, indices=s)
+    want = np.where(np.isinf(ref), oracle.UNREACHABLE, ref).astype(np.uint32)
+    assert np.array_equal(oracle.bfs(g, s), want)
