@@ -167,6 +167,15 @@ int mlmq_features_host(int32_t n, int64_t m, const int32_t* row_offsets, const i
 int mlmq_sssp(const mlmq_graph* g, uint32_t source, uint32_t* dist_out, const mlmq_config* cfg);
 
 /*
+ * Breadth-first search levels on the same queues (Section 5.7, BFS case
+ * study): levels_out[v] = fewest edges on a path from source, MLMQ_UNREACHABLE
+ * where none; the weights of g are ignored. Buffers, streams and errors as for
+ * mlmq_sssp. cfg NULL = the graph's config with its near-far window set to one
+ * level and its bucket width to 1.
+ */
+int mlmq_bfs(const mlmq_graph* g, uint32_t source, uint32_t* levels_out, const mlmq_config* cfg);
+
+/*
  * Many queries in one persistent launch. Query i solves graphs[i] from
  * sources[i] into dist_outs[i] (device memory, n_i uint32 each). cfgs may be
  * NULL (per-graph autotuned/default) or hold one config per query; launch

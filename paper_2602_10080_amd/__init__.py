@@ -36,7 +36,7 @@ MEM_HOST, MEM_DEVICE = 0, 1
 # C-ABI entry points declared in include/mlmq.h
 EXPORTS = (
     "mlmq_config_default", "mlmq_graph_create", "mlmq_graph_destroy", "mlmq_graph_info", "mlmq_graph_config",
-    "mlmq_features_host", "mlmq_sssp", "mlmq_sssp_batch", "mlmq_autotune", "mlmq_server_create",
+    "mlmq_features_host", "mlmq_sssp", "mlmq_bfs", "mlmq_sssp_batch", "mlmq_autotune", "mlmq_server_create",
     "mlmq_server_submit", "mlmq_server_poll", "mlmq_server_wait", "mlmq_server_times",
     "mlmq_server_destroy", "mlmq_last_error",
 )
@@ -110,6 +110,7 @@ def _declare(lib):
                                            ctypes.POINTER(Features)]),
         "mlmq_features_host": (ctypes.c_int, [i32, i64, vp, vp, vp, ctypes.POINTER(Features)]),
         "mlmq_sssp": (ctypes.c_int, [vp, u32, vp, ctypes.POINTER(Config)]),
+        "mlmq_bfs": (ctypes.c_int, [vp, u32, vp, ctypes.POINTER(Config)]),
         "mlmq_sssp_batch": (ctypes.c_int, [vp, vp, vp, i32, vp, vp]),
         "mlmq_autotune": (ctypes.c_int, [vp, u32, ctypes.POINTER(Config)]),
         "mlmq_server_create": (ctypes.c_int, [vp, i32, u64, i32, ctypes.POINTER(Config), ctypes.POINTER(vp)]),
@@ -264,6 +265,23 @@ def sssp(graph: Graph, source: int, out=None, config: Optional[Config] = None, s
     """Shortest distances from source into out (device tensor allocated if None,
     or a host uint32 numpy array). config None = the graph's tuned/default
     config. Returns out, or (out, stats dict) when stats=True."""
+    return _single("mlmq_sssp", graph, source, out, config, stream, stats)
+
+
+def bfs(graph: Graph, source: int, out=None, config: Optional[Config] = None, stream=None,
+        stats: bool = False):
+    """Breadth-first levels (fewest edges) from source; weights are ignored.
+    config None = the graph's config with a one-level near-far window and
+    unit bucket width (what mlmq_bfs uses for a NULL config)."""
+    if config is None:
+        config = graph.config()
+        config.delta1 = 1
+        config.delta2_log2 = 0
+        config.relax_mode = RELAX_PRECHECK
+    return _single("mlmq_bfs", graph, source, out, config, stream, stats)
+
+
+def _single(fn: str, graph: Graph, source: int, out, config: Optional[Config], stream, stats: bool):
     if out is None:
         out = new_dist(graph.n)
     if hasattr(out, "is_cuda"):
@@ -283,7 +301,7 @@ def sssp(graph: Graph, source: int, out=None, config: Optional[Config] = None, s
         st = Stats()
         st.struct_size = ctypes.sizeof(Stats)
         cfg.stats_out = ctypes.pointer(st)
-    _check(lib().mlmq_sssp(graph.handle, int(source), ptr, ctypes.byref(cfg)))
+    _check(getattr(lib(), fn)(graph.handle, int(source), ptr, ctypes.byref(cfg)))
     if stats:
         return out, st.as_dict()
     return out

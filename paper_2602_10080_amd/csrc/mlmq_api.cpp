@@ -728,7 +728,7 @@ void heuristic_config(const mlmq_graph* g, mlmq_config* c) {
 }
 
 // One solve attempt sequence (with capacity retries) on a slab.
-int run_single(const mlmq_graph* g, uint32_t source, uint32_t* dist_out, const mlmq_config& c) {
+int run_single(const mlmq_graph* g, uint32_t source, uint32_t* dist_out, const mlmq_config& c, bool unit_weights) {
   int rc = check_config(&c);
   if (rc) return rc;
   hipStream_t stream = reinterpret_cast<hipStream_t>(c.stream);
@@ -756,6 +756,7 @@ int run_single(const mlmq_graph* g, uint32_t source, uint32_t* dist_out, const m
     QueryCtrl* h_ctrl = reinterpret_cast<QueryCtrl*>(slab->host);
     QueryDesc* h_desc = reinterpret_cast<QueryDesc*>(static_cast<char*>(slab->host) + sizeof(QueryCtrl));
     *h_desc = make_desc(g, c, p, base, d_dist, source, shape.grid);
+    h_desc->unit_w = unit_weights ? 1u : 0u;
     uint32_t* d_beats = reinterpret_cast<uint32_t*>(base + beats_off);
     LaunchArgs a = make_args(d_desc, d_batch, 1, shape, c.timeout_ms, d_beats);
     hipEvent_t ev0 = nullptr, evw = nullptr, ev1 = nullptr;
@@ -847,4 +848,21 @@ extern "C" int mlmq_sssp(const mlmq_graph* g, uint32_t source, uint32_t* dist_ou
   mlmq_config tmp;
   const mlmq_config* c = resolve_config(g, cfg, &tmp);
   return run_single(g, source, dist_out, *c);
+}
+
+extern "C" int mlmq_bfs(const mlmq_graph* g, uint32_t source, uint32_t* levels_out, const mlmq_config* cfg) {
+  if (!g) return set_error(MLMQ_ERR_INVALID_ARG, "graph is NULL");
+  if (!levels_out) return set_error(MLMQ_ERR_INVALID_ARG, "levels_out is NULL");
+  if (source >= (uint32_t)g->n) return set_error(MLMQ_ERR_INVALID_ARG, "source %u >= n %d", source, g->n);
+  int rc = need_device();
+  if (rc) return rc;
+  mlmq_config tmp;
+  if (cfg) return run_single(g, source, levels_out, *cfg, true);
+  // the graph's config with its weight-dependent windows set for unit steps:
+  // the near set of a near-far L1 is the current level
+  tmp = *resolve_config(g, nullptr, &tmp);
+  tmp.delta1 = 1;
+  tmp.delta2_log2 = 0;
+  tmp.relax_mode = MLMQ_RELAX_PRECHECK;
+  return run_single(g, source, levels_out, tmp, true);
 }

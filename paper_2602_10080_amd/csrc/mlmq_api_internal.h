@@ -83,7 +83,8 @@ LaunchArgs make_args(const QueryDesc* d_desc, BatchCtrl* d_batch, int nq, const 
 int status_to_code(uint32_t st);
 std::string describe_query_state(const QueryDesc& d, const uint32_t* d_beats, uint32_t nbeats);
 void fill_stats(mlmq_stats* st, const QueryCtrl& h, double ms, double worker_ms, uint32_t grid, uint32_t retries);
-int run_single(const mlmq_graph* g, uint32_t source, uint32_t* dist_out, const mlmq_config& c);
+int run_single(const mlmq_graph* g, uint32_t source, uint32_t* dist_out, const mlmq_config& c,
+               bool unit_weights = false);
 // What the host watchdog snapshots when a launch overruns its deadline.
 struct WatchdogView {
   const QueryCtrl* d_ctrl = nullptr;  // first query's control block

@@ -102,6 +102,8 @@ struct QueryDesc {
   uint32_t hub_chunk;
   uint32_t want_wgs;   // workgroups this query should get
   uint32_t relax_mode; // MLMQ_RELAX_*
+  uint32_t unit_w;     // 1: every edge weighs 1 (breadth-first levels)
+  uint32_t pad;
 };
 
 // Batch-wide control (device memory).

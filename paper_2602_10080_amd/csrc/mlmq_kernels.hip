@@ -762,7 +762,7 @@ __device__ __forceinline__ void relax_many(Ctx& c, const bool (&has)[U], const u
   bool of = false;
 #pragma unroll
   for (int u = 0; u < U; ++u) {
-    const uint64_t sum = (uint64_t)d[u] + (a[u] >> 32);
+    const uint64_t sum = (uint64_t)d[u] + (c.q.unit_w ? 1ull : (a[u] >> 32));
     of = of || (has[u] && sum >= kInf);
     cand[u] = has[u] && sum < kInf;
     v[u] = (uint32_t)a[u];

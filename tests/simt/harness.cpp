@@ -44,7 +44,7 @@ T* zalloc(size_t count) {
 }  // namespace
 
 // knobs: l0_rows, l1_type, l2_type, l1_cap, l1_wb, delta1, d2_log2, bmax, bnum,
-//        th_v, th_hub, hub_chunk, nb_log2, hub_cap, timeout_ms, relax_mode
+//        th_v, th_hub, hub_chunk, nb_log2, hub_cap, timeout_ms, relax_mode, unit_w
 extern "C" int sim_sssp(int32_t n, const int32_t* off, const int32_t* col, const uint32_t* w, uint32_t src,
                         uint32_t* dist, const uint32_t* k, uint32_t nwg, uint32_t wg_size, uint64_t* stats,
                         uint32_t* status) {
@@ -91,6 +91,7 @@ extern "C" int sim_sssp(int32_t n, const int32_t* off, const int32_t* col, const
   q->hub_chunk = k[11];
   q->want_wgs = nwg;
   q->relax_mode = k[15];
+  q->unit_w = k[16];
   // init kernel, serially over its threads (it has no cross-lane operations)
   const uint32_t blocks = 4;
   simt::gdim = dim3(blocks, 1);
@@ -301,6 +302,7 @@ extern "C" int sim_server(int32_t n, const int32_t* off, const int32_t* col, con
         q.hub_chunk = k[11];
         q.want_wgs = want;
         q.relax_mode = k[15];
+        q.unit_w = k[16];
         __atomic_store_n(&done[s], 0ull, __ATOMIC_RELEASE);
         simt::gdim = dim3(4, 1);
         simt::bdim = dim3(256);

@@ -101,3 +101,16 @@ def test_serving_mix_on_serving_graphs():
     assert status == [0] * len(reqs)
     for (g, s), o in zip(reqs, outs):
         assert np.array_equal(mlmq.to_numpy(o), oracle.dijkstra(csrs[g], s)), (g, s)
+
+
+def test_bfs_rmat23_and_road_grid2048():
+    """Breadth-first levels at the benchmark's sizes equal the oracle's BFS."""
+    mlmq = _mlmq()
+    for name, csr, src in [("grid2048", gg.grid(2048, 2048, 0.05, seed=1), 1024 * 2048 + 1024),
+                           ("rmat23", (c := gg.rmat(23, 16, seed=1)), gg.max_degree_vertex(c))]:
+        g = mlmq.Graph.from_csr(csr)
+        _say(f"[full] bfs {name}")
+        out = mlmq.bfs(g, src)
+        torch.cuda.synchronize()
+        assert np.array_equal(mlmq.to_numpy(out), oracle.bfs(csr, src)), name
+        g.close()

@@ -195,3 +195,17 @@ def test_batch_matches_alone(dev_graphs, oracle_dist):
     assert status2 == [0] * len(names)
     for o1, o2 in zip(outs, outs2):
         assert torch.equal(o1, o2)
+
+
+@pytest.mark.parametrize("cfg_name", [None, "L0x2-L1V-L2V", "L0x1-L1NF-L2DQ", "L0x1-L1SLF-L2V", "L0off-L1NF-L2V-atomic"])
+@pytest.mark.parametrize("graph_name", ["grid64", "road96x80", "rmat12", "uniform", "path", "star", "isolated_src",
+                                        "multi"])
+def test_bfs_parity(dev_graphs, graph_name, cfg_name):
+    """Breadth-first levels on the same queues (Section 5.7) equal the oracle's BFS."""
+    mlmq = _mlmq()
+    g, csr, src = dev_graphs[graph_name]
+    _say(f"[bfs] graph={graph_name} cfg={cfg_name}")
+    cfg = None if cfg_name is None else mlmq.default_config(**CONFIGS[cfg_name], timeout_ms=10000)
+    out = mlmq.bfs(g, src, config=cfg)
+    torch.cuda.synchronize()
+    assert np.array_equal(mlmq.to_numpy(out), oracle.bfs(csr, src))
