@@ -261,31 +261,13 @@ extern "C" int mlmq_graph_create(int32_t n, int64_t m, const int32_t* row_offset
   g->overflow_safe = (uint64_t)(n - 1) * (uint64_t)maxw < (uint64_t)kInf;
   std::vector<uint64_t> adj((size_t)m);
   for (int64_t e = 0; e < m; ++e) adj[e] = (uint32_t)hcol[e] | ((uint64_t)hw[e] << 32);
-  // Low-degree graphs (meshes, road-like grids) also get fixed-width rows:
-  // row v starts at v * W, so a vertex's edges are loaded together with its
-  // label, without waiting for its row offsets (one memory round trip less
-  // per hop on the latency-bound critical path).
-  std::vector<uint64_t> ell;
-  const uint32_t maxdeg = (uint32_t)g->features.max_deg;
-  if (m > 0 && maxdeg <= kEllMaxW) {
-    uint32_t wd = 1;
-    while (wd < maxdeg) wd <<= 1;
-    g->ell_w = wd;
-    ell.assign((size_t)n * wd, kNoEdge);
-    for (int32_t v = 0; v < n; ++v)
-      for (int32_t k = 0; k < hoff[v + 1] - hoff[v]; ++k) ell[(size_t)v * wd + k] = adj[(size_t)hoff[v] + k];
-  }
   hipError_t e = hipMalloc(&g->d_off, sizeof(int32_t) * ((size_t)n + 1));
   if (e == hipSuccess) e = hipMalloc(&g->d_adj, sizeof(uint64_t) * std::max<int64_t>(m, 1));
-  if (e == hipSuccess && g->ell_w) e = hipMalloc(&g->d_ell, sizeof(uint64_t) * ell.size());
   if (e == hipSuccess) e = hipMemcpy(g->d_off, hoff, sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice);
   if (e == hipSuccess && m) e = hipMemcpy(g->d_adj, adj.data(), sizeof(uint64_t) * m, hipMemcpyHostToDevice);
-  if (e == hipSuccess && g->ell_w)
-    e = hipMemcpy(g->d_ell, ell.data(), sizeof(uint64_t) * ell.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     (void)hipFree(g->d_off);
     (void)hipFree(g->d_adj);
-    (void)hipFree(g->d_ell);
     return hip_fail(e, "uploading graph");
   }
   *out = g.release();
@@ -296,7 +278,6 @@ extern "C" void mlmq_graph_destroy(mlmq_graph* g) {
   if (!g) return;
   (void)hipFree(g->d_off);
   (void)hipFree(g->d_adj);
-  (void)hipFree(g->d_ell);
   delete g;
 }
 
@@ -369,8 +350,6 @@ QueryDesc make_desc(const mlmq_graph* g, const mlmq_config& c, const QueryPlan& 
   std::memset(&d, 0, sizeof(d));
   d.off = g->d_off;
   d.adj = g->d_adj;
-  d.ell = g->d_ell;
-  d.ell_w = g->ell_w;
   d.dist = dist;
   d.ctrl = reinterpret_cast<QueryCtrl*>(base + p.off_ctrl);
   d.rings = reinterpret_cast<RingCtr*>(base + p.off_rings);

@@ -17,8 +17,6 @@ struct mlmq_graph {
   int64_t m = 0;
   int32_t* d_off = nullptr;   // [n+1]
   uint64_t* d_adj = nullptr;  // [m] col | weight << 32
-  uint64_t* d_ell = nullptr;  // [n * ell_w] fixed-width rows (low-degree graphs), padded with kNoEdge
-  uint32_t ell_w = 0;
   mlmq_features features{};
   uint64_t deg_hist[33]{};    // bucket k: degrees in [2^(k-1), 2^k), bucket 0: degree 0
   uint32_t max_w = 0;

@@ -12,8 +12,6 @@ constexpr uint32_t kInf = 0xFFFFFFFFu;  // unreachable / "no ticket"
 constexpr int kMaxBuckets = 64;         // L2 buckets: one per lane of a scanning wave
 constexpr int kMaxL0Rows = 4;           // L0 register rows of 64 elements
 constexpr uint32_t kStageB = 8;         // buckets after the head with a write-combining row
-constexpr uint32_t kEllMaxW = 4;        // widest fixed-width row layout built for low-degree graphs
-constexpr uint64_t kNoEdge = 0xFFFFFFFFull;  // padding slot of a fixed-width row (col = UINT32_MAX)
 
 // Device status word of a query (ctrl->error).
 enum : uint32_t {
@@ -105,8 +103,7 @@ struct QueryDesc {
   uint32_t want_wgs;   // workgroups this query should get
   uint32_t relax_mode; // MLMQ_RELAX_*
   uint32_t unit_w;     // 1: every edge weighs 1 (breadth-first levels)
-  uint32_t ell_w;      // > 0: rows also stored as ell[v * ell_w + k] (padded with kNoEdge)
-  const uint64_t* ell; // [n * ell_w] fixed-width rows of a low-degree graph, or null
+  uint32_t pad;
 };
 
 // Batch-wide control (device memory).

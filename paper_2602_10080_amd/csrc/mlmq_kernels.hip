@@ -831,70 +831,11 @@ __device__ __forceinline__ void flat_edge(uint32_t idx, uint32_t incl, uint32_t 
   dd = (uint32_t)__shfl(d, (int)j);
 }
 
-// Relaxation of a batch on a low-degree graph with fixed-width rows: each
-// lane loads its vertex's label and all W row slots at once (no row offsets
-// needed first), drops the item if it is stale, relaxes every real edge, and
-// the W results go through the Write cascade one slot at a time.
-template <int W>
-__device__ __forceinline__ void process_ell(Ctx& c, uint64_t e, bool ok) {
-  const uint32_t v = elem_v(e), d = elem_d(e);
-  const uint32_t lv = ok ? v : 0u;
-  const uint64_t eoff = (uint64_t)lv * W;
-  uint64_t a[W];
-#pragma unroll
-  for (int k = 0; k < W; ++k) a[k] = c.q.ell[eoff + k];
-  const uint32_t label = ld_label(c.q.dist + lv);
-  const bool stale = ok && d > label;
-  const bool live = ok && !stale;
-  c.ct[kCtStale] += popc(ballot(stale));
-  c.ct[kCtExpansions] += popc(ballot(live));
-  uint32_t vv[W], nd[W], lab[W];
-  bool cand[W];
-  bool of = false;
-  uint32_t nedges = 0;
-#pragma unroll
-  for (int k = 0; k < W; ++k) {
-    const bool has = live && a[k] != kNoEdge;
-    nedges += popc(ballot(has));
-    const uint64_t sum = (uint64_t)d + (c.q.unit_w ? 1ull : (a[k] >> 32));
-    of = of || (has && sum >= kInf);
-    cand[k] = has && sum < kInf;
-    vv[k] = (uint32_t)a[k];
-    nd[k] = (uint32_t)sum;
-    const uint32_t lw = cand[k] ? vv[k] : 0u;
-    lab[k] = c.q.relax_mode == MLMQ_RELAX_ATOMIC ? kInf : ld_label(c.q.dist + lw);
-  }
-  c.ct[kCtEdges] += nedges;
-  if (ballot(of)) c.ovf = true;
-  bool imp[W];
-  uint32_t natom = 0;
-#pragma unroll
-  for (int k = 0; k < W; ++k) natom += popc(ballot(cand[k] && nd[k] < lab[k]));
-  c.ct[kCtAtomics] += natom;
-#pragma unroll
-  for (int k = 0; k < W; ++k) {
-    imp[k] = false;
-    if (cand[k] && nd[k] < lab[k]) {
-      const uint32_t old =
-          __hip_atomic_fetch_min(c.q.dist + vv[k], nd[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      imp[k] = nd[k] < old;
-    }
-  }
-#pragma unroll
-  for (int k = 0; k < W; ++k) emit(c, vv[k], nd[k], imp[k]);
-}
-
 // Relaxation of a batch (the paper's SSSP_relax with the load balancing of
 // Section 4.1): drop stale items, send very-high-degree vertices to the
 // grid-wide tier, let the whole wave sweep vertices above th_v, and spread the
 // edges of the remaining vertices evenly over the lanes.
 __device__ __forceinline__ void process_vec(Ctx& c, uint64_t e, bool ok) {
-  switch (c.q.ell_w) {
-    case 1: process_ell<1>(c, e, ok); return;
-    case 2: process_ell<2>(c, e, ok); return;
-    case 4: process_ell<4>(c, e, ok); return;
-    default: break;
-  }
   const uint32_t v = elem_v(e), d = elem_d(e);
   // label and row bounds are loaded together (vertex 0 for idle lanes)
   const uint32_t lv = ok ? v : 0u;

@@ -25,12 +25,8 @@ def transformed_source(checked: bool = False) -> str:
         src = src.replace("c.q.dist + v[u]", "c.q.dist + simt_chk(v[u], c.q.n, \"dist\", __LINE__)")
         src = src.replace("c.q.dist + hv", "c.q.dist + simt_chk(hv, c.q.n, \"dist\", __LINE__)")
         src = src.replace("ld_label(c.q.dist + v)", "ld_label(c.q.dist + simt_chk(v, c.q.n, \"dist\", __LINE__))")
-        src = src.replace("c.q.ell[eoff + k]",
-                          "c.q.ell[simt_chk(eoff + k, (uint64_t)c.q.n * W, \"ell\", __LINE__)]")
-        src = src.replace("c.q.dist + vv[k]", "c.q.dist + simt_chk(vv[k], c.q.n, \"dist\", __LINE__)")
-        src = src.replace("c.q.dist + lw", "c.q.dist + simt_chk(lw, c.q.n, \"dist\", __LINE__)")
         for pat in ("c.q.adj[eidx]", "c.q.off[lv]", "c.q.dist + lv", "c.q.dist + v[u]", "c.q.dist + hv",
-                    "ld_label(c.q.dist + v)", "c.q.ell[eoff + k]", "c.q.dist + vv[k]", "c.q.dist + lw"):
+                    "ld_label(c.q.dist + v)"):
             assert pat in open(KERNEL).read(), pat
     src = src.replace("extern __shared__ uint64_t smem[];",
                       "uint64_t* smem = reinterpret_cast<uint64_t*>(simt::group->lds);")

@@ -1,6 +1,5 @@
 // Runs the library's init and persistent worker kernels on the CPU (one host
 // thread per lane) for small graphs. Test infrastructure only.
-#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <cstdio>
@@ -44,24 +43,8 @@ T* zalloc(size_t count) {
 }
 }  // namespace
 
-// Fixed-width rows (as the library builds them for graphs of degree <= 4).
-static std::vector<uint64_t> make_ell(int32_t n, const int32_t* off, const std::vector<uint64_t>& adj,
-                                      uint32_t* width) {
-  int32_t maxdeg = 0;
-  for (int32_t v = 0; v < n; ++v) maxdeg = std::max(maxdeg, off[v + 1] - off[v]);
-  uint32_t w = 1;
-  while ((int32_t)w < maxdeg) w <<= 1;
-  *width = 0;
-  if (maxdeg > (int32_t)kEllMaxW || off[n] == 0) return {};
-  std::vector<uint64_t> ell((size_t)n * w, kNoEdge);
-  for (int32_t v = 0; v < n; ++v)
-    for (int32_t k = 0; k < off[v + 1] - off[v]; ++k) ell[(size_t)v * w + k] = adj[(size_t)off[v] + k];
-  *width = w;
-  return ell;
-}
-
 // knobs: l0_rows, l1_type, l2_type, l1_cap, l1_wb, delta1, d2_log2, bmax, bnum,
-//        th_v, th_hub, hub_chunk, nb_log2, hub_cap, timeout_ms, relax_mode, unit_w, fixed-width rows
+//        th_v, th_hub, hub_chunk, nb_log2, hub_cap, timeout_ms, relax_mode, unit_w
 extern "C" int sim_sssp(int32_t n, const int32_t* off, const int32_t* col, const uint32_t* w, uint32_t src,
                         uint32_t* dist, const uint32_t* k, uint32_t nwg, uint32_t wg_size, uint64_t* stats,
                         uint32_t* status) {
@@ -109,10 +92,6 @@ extern "C" int sim_sssp(int32_t n, const int32_t* off, const int32_t* col, const
   q->want_wgs = nwg;
   q->relax_mode = k[15];
   q->unit_w = k[16];
-  uint32_t ell_w = 0;
-  std::vector<uint64_t> ell = k[17] ? make_ell(n, off, adj, &ell_w) : std::vector<uint64_t>();
-  q->ell_w = ell_w;
-  q->ell = ell_w ? ell.data() : nullptr;
   // init kernel, serially over its threads (it has no cross-lane operations)
   const uint32_t blocks = 4;
   simt::gdim = dim3(blocks, 1);
@@ -271,8 +250,6 @@ extern "C" int sim_server(int32_t n, const int32_t* off, const int32_t* col, con
     uint64_t *hdr, *data, *hub_rec;
     uint32_t *hub_cur, *hub_pub;
   };
-  uint32_t ell_w = 0;
-  std::vector<uint64_t> ell = k[17] ? make_ell(n, off, adj, &ell_w) : std::vector<uint64_t>();
   std::vector<int32_t> slot_q(nslots, -1);
   std::vector<uint32_t> slot_gen(nslots, 0);
   std::vector<Mem> slot_mem(nslots);
@@ -326,8 +303,6 @@ extern "C" int sim_server(int32_t n, const int32_t* off, const int32_t* col, con
         q.want_wgs = want;
         q.relax_mode = k[15];
         q.unit_w = k[16];
-        q.ell_w = ell_w;
-        q.ell = ell_w ? ell.data() : nullptr;
         __atomic_store_n(&done[s], 0ull, __ATOMIC_RELEASE);
         simt::gdim = dim3(4, 1);
         simt::bdim = dim3(256);

@@ -17,22 +17,19 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 
 # knobs: l0_rows, l1_type, l2_type, l1_cap, l1_wb, delta1, d2_log2, bmax, bnum,
-#        th_v, th_hub, hub_chunk, nb_log2, hub_cap, timeout_ms, relax_mode, unit_w, fixed-width rows
+#        th_v, th_hub, hub_chunk, nb_log2, hub_cap, timeout_ms, relax_mode, unit_w
 CFG = {
-    "L0x2-L1V-L2V": [2, 1, 0, 1024, 64, 256, 7, 32, 4, 32, 0, 2048, 10, 1, 60000, 0, 0, 0],
-    "L0off-L1none-L2V": [0, 0, 0, 1024, 64, 256, 7, 32, 4, 32, 0, 2048, 10, 1, 60000, 0, 0, 0],
-    "L0x4-L1V-wb4-tiny": [4, 1, 0, 64, 4, 256, 7, 32, 4, 32, 0, 2048, 4, 1, 60000, 0, 0, 0],
-    "L1NF-L2V": [1, 2, 0, 1024, 0, 64, 7, 32, 4, 32, 0, 2048, 10, 1, 60000, 0, 0, 0],
-    "L1FQ-L2V": [1, 3, 0, 1024, 0, 64, 7, 32, 4, 32, 0, 2048, 10, 1, 60000, 0, 0, 0],
-    "L1NF-L2DQ": [1, 2, 1, 1024, 0, 32, 5, 32, 2, 32, 0, 2048, 8, 1, 60000, 0, 0, 0],
-    "L1FQ-L2DQ-hub": [1, 3, 1, 1024, 0, 128, 8, 8, 8, 32, 128, 128, 8, 256, 60000, 0, 0, 0],
-    "L1V-L2V-hub64": [2, 1, 0, 1024, 64, 256, 7, 32, 4, 8, 64, 64, 10, 256, 60000, 0, 0, 0],
-    "L0off-L1NF-L2V-atomic": [0, 2, 0, 256, 0, 64, 7, 32, 4, 32, 0, 2048, 10, 1, 60000, 1, 0, 0],
-    "L0x1-L1SLF-L2V": [1, 4, 0, 128, 0, 64, 7, 32, 4, 32, 0, 2048, 10, 1, 60000, 0, 0, 0],
-    "L0off-L1NF-L2V-atomic-ell": [0, 2, 0, 256, 0, 64, 7, 32, 4, 32, 0, 2048, 10, 1, 60000, 1, 0, 1],
-    "L0x2-L1V-L2V-ell": [2, 1, 0, 1024, 64, 256, 7, 32, 4, 32, 0, 2048, 10, 1, 60000, 0, 0, 1],
-    "L1FQ-L2DQ-ell": [1, 3, 1, 1024, 0, 128, 8, 8, 2, 32, 0, 2048, 8, 1, 60000, 0, 0, 1],
-    "L0x1-L1SLF-L2DQ-hub": [1, 4, 1, 256, 0, 64, 6, 16, 1, 16, 128, 128, 8, 256, 60000, 0, 0, 0],
+    "L0x2-L1V-L2V": [2, 1, 0, 1024, 64, 256, 7, 32, 4, 32, 0, 2048, 10, 1, 60000, 0, 0],
+    "L0off-L1none-L2V": [0, 0, 0, 1024, 64, 256, 7, 32, 4, 32, 0, 2048, 10, 1, 60000, 0, 0],
+    "L0x4-L1V-wb4-tiny": [4, 1, 0, 64, 4, 256, 7, 32, 4, 32, 0, 2048, 4, 1, 60000, 0, 0],
+    "L1NF-L2V": [1, 2, 0, 1024, 0, 64, 7, 32, 4, 32, 0, 2048, 10, 1, 60000, 0, 0],
+    "L1FQ-L2V": [1, 3, 0, 1024, 0, 64, 7, 32, 4, 32, 0, 2048, 10, 1, 60000, 0, 0],
+    "L1NF-L2DQ": [1, 2, 1, 1024, 0, 32, 5, 32, 2, 32, 0, 2048, 8, 1, 60000, 0, 0],
+    "L1FQ-L2DQ-hub": [1, 3, 1, 1024, 0, 128, 8, 8, 8, 32, 128, 128, 8, 256, 60000, 0, 0],
+    "L1V-L2V-hub64": [2, 1, 0, 1024, 64, 256, 7, 32, 4, 8, 64, 64, 10, 256, 60000, 0, 0],
+    "L0off-L1NF-L2V-atomic": [0, 2, 0, 256, 0, 64, 7, 32, 4, 32, 0, 2048, 10, 1, 60000, 1, 0],
+    "L0x1-L1SLF-L2V": [1, 4, 0, 128, 0, 64, 7, 32, 4, 32, 0, 2048, 10, 1, 60000, 0, 0],
+    "L0x1-L1SLF-L2DQ-hub": [1, 4, 1, 256, 0, 64, 6, 16, 1, 16, 128, 128, 8, 256, 60000, 0, 0],
 }
 
 
