@@ -121,6 +121,24 @@ def summarize(name, desc, csr, src, res, cfg):
     )
 
 
+def bench_bfs(mlmq, torch, csr, src, steps=5):
+    """Breadth-first levels on the same queues (same graph, same source)."""
+    g = mlmq.Graph.from_csr(csr)
+    out = mlmq.new_dist(csr.n)
+    mlmq.bfs(g, src, out=out)
+    torch.cuda.synchronize()
+    wms = []
+    for _ in range(steps):
+        _, st = mlmq.bfs(g, src, out=out, stats=True)
+        wms.append(st["worker_ms"])
+    torch.cuda.synchronize()
+    _, m_reach = reach(csr, mlmq.to_numpy(out))
+    g.close()
+    w = statistics.median(wms)
+    log(f"[bench] bfs: {w:.2f} ms, {m_reach / w / 1e6:.2f} GTEPS")
+    return dict(worker_ms=w, gteps_device=m_reach / w / 1e6, work_ratio=st["expansions"] / max(1, reach(csr, mlmq.to_numpy(out))[0]))
+
+
 def cpu_baseline(csr, src, gpu_dist, max_seconds=30.0):
     """Oracle Dijkstra on one core; repeated while under the time bound."""
     import oracle
@@ -337,6 +355,8 @@ def main():
             s["cpu_baseline"] = cb
             s["verified_against_oracle"] = ok
             log(f"[bench] {name}: oracle {cb['seconds']:.2f} s ({cb['value']:.4f} GTEPS), match={ok}")
+        if name in ("rmat23", "grid2048"):
+            s["bfs"] = bench_bfs(mlmq, torch, csr, src)
         results[name] = s
         if i == 0:
             primary = s
