@@ -741,22 +741,18 @@ __device__ __forceinline__ void emit(Ctx& c, uint32_t v, uint32_t nd, bool imp) 
 // in flight instead of one.
 constexpr int kRelaxUnroll = 4;
 
-// Relax U sub-batches of 64 edges (one edge per lane each; the relax step of
-// the paper's kernel sketch, with atomicMin): candidate nd = d + w
+// Relax U sub-batches of 64 edges, given as packed edge words (one edge per
+// lane each; the relax step of the paper's kernel sketch, with atomicMin):
+// candidate nd = d + w
 // (saturating), a plain load of dist[v] filters hopeless candidates (unless
 // the query relaxes by atomicMin alone), then atomicMin decides; a lane has
 // new work iff nd < the previous label.
-// Lanes without an edge load entry 0 of adj / dist (both exist whenever
-// there is an edge to relax) so that every load is unconditional.
+// Lanes without a candidate load the label of vertex 0 (and, in relax_many,
+// edge word 0): both exist whenever there is an edge to relax, so every load
+// is unconditional.
 template <int U>
-__device__ __forceinline__ void relax_many(Ctx& c, const bool (&has)[U], const uint32_t (&ed)[U],
-                                           const uint32_t (&d)[U]) {
-  uint64_t a[U];
-#pragma unroll
-  for (int u = 0; u < U; ++u) {
-    const uint32_t eidx = has[u] ? ed[u] : 0u;
-    a[u] = c.q.adj[eidx];
-  }
+__device__ __forceinline__ void relax_words(Ctx& c, const bool (&has)[U], const uint64_t (&a)[U],
+                                            const uint32_t (&d)[U]) {
   uint32_t v[U], nd[U], lab[U];
   bool cand[U];
   bool of = false;
@@ -793,23 +789,63 @@ __device__ __forceinline__ void relax_many(Ctx& c, const bool (&has)[U], const u
   for (int u = 0; u < U; ++u) emit(c, v[u], nd[u], imp[u]);
 }
 
+// The same for edges given by their CSR positions: the packed edge words are
+// loaded first.
+template <int U>
+__device__ __forceinline__ void relax_many(Ctx& c, const bool (&has)[U], const uint32_t (&ed)[U],
+                                           const uint32_t (&d)[U]) {
+  uint64_t a[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const uint32_t eidx = has[u] ? ed[u] : 0u;
+    a[u] = c.q.adj[eidx];
+  }
+  relax_words<U>(c, has, a, d);
+}
+
 // Whole wave sweeps the edge range [eb, ee) of vertex v at distance d. Every
-// 1024 edges it looks at dist[v] again: once v has been improved, the rest of
+// 1024 edges it looks at dist[v] again (the load goes out with that step's
+// label loads and is read after it): once v has been improved, the rest of
 // the sweep is redundant (the improved item expands all of it anyway).
 __device__ __forceinline__ void process_range(Ctx& c, uint32_t v, uint32_t d, uint32_t eb, uint32_t ee) {
   constexpr int U = kRelaxUnroll;
   uint32_t x = eb;
-  for (; x + 64u * U <= ee && !c.stop; x += 64u * U) {
-    if (x != eb && ((x - eb) & 1023u) == 0 && uni(ld_label(c.q.dist + v)) < d) break;
-    bool has[U];
-    uint32_t ed[U], dd[U];
+  if (x + 64u * U <= ee && !c.stop) {
+    // the edge words of the next step are loaded before the current step is
+    // relaxed, so their latency overlaps the label loads and atomics
+    uint64_t nx[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      has[u] = true;
-      ed[u] = x + 64u * u + lane();
-      dd[u] = d;
+      const uint32_t eidx = x + 64u * u + lane();
+      nx[u] = c.q.adj[eidx];
     }
-    relax_many<U>(c, has, ed, dd);
+    for (;;) {
+      uint64_t a[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) a[u] = nx[u];
+      const uint32_t xn = x + 64u * U;
+      const bool more = xn + 64u * U <= ee;
+      if (more) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const uint32_t eidx = xn + 64u * u + lane();
+          nx[u] = c.q.adj[eidx];
+        }
+      }
+      const bool chk = x != eb && ((x - eb) & 1023u) == 0;
+      const uint32_t cur = chk ? ld_label(c.q.dist + v) : kInf;
+      bool has[U];
+      uint32_t dd[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        has[u] = true;
+        dd[u] = d;
+      }
+      relax_words<U>(c, has, a, dd);
+      x = xn;
+      if (!more || c.stop) break;
+      if (chk && uni(cur) < d) return;
+    }
   }
   for (; x < ee && !c.stop; x += 64) {
     bool has[1] = {x + lane() < ee};
@@ -1093,8 +1129,11 @@ __device__ __forceinline__ QueryDesc load_desc_coherent(const QueryDesc* d) {
 
 // ------------------------------------------------------------ kernels
 
-// One wave per workgroup; dynamic LDS = staging row + L1 ring(s).
-__global__ void __launch_bounds__(64) mlmq_worker(LaunchArgs a) {
+// One wave per workgroup; dynamic LDS = staging row + L1 ring(s). Three waves
+// per SIMD are asked of the register allocator: the worker runs up to 12
+// workgroups per CU (batches and the server fill the device), and the limit
+// also measured faster at the default launch sizes.
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) mlmq_worker(LaunchArgs a) {
   extern __shared__ uint64_t smem[];
   const uint64_t t0 = (uint64_t)wall_clock64();
   uint32_t* const my_beat = a.beats ? a.beats + blockIdx.x : nullptr;
@@ -1115,7 +1154,7 @@ __global__ void __launch_bounds__(64) mlmq_worker(LaunchArgs a) {
 // works on that query until it terminates, and leaves. Idle waves sleep and
 // leave the kernel on the host's stop flag or after idle_exit_ticks without
 // work (the host relaunches the kernel when work arrives and none is left).
-__global__ void __launch_bounds__(64) mlmq_server_worker(ServerArgs a) {
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) mlmq_server_worker(ServerArgs a) {
   extern __shared__ uint64_t smem[];
   uint64_t last_busy = (uint64_t)wall_clock64();
   uint32_t idle = 0;
