@@ -98,9 +98,19 @@ def measure(mlmq, torch, csr, src, overrides, steps, warmup):
         wms.append(st["worker_ms"])
         last = st
     total = time.perf_counter() - t_all
+    # device optimality check of the output; its edge pass (every edge word and
+    # both labels read once) is the cost of one relaxation sweep of the graph
+    viol, pass_ms = None, []
+    try:
+        for _ in range(4):
+            viol, ms = mlmq.check(g, src, out, stream=stream)
+            pass_ms.append(ms)
+    except mlmq.MlmqError as e:
+        log(f"[bench] device check unavailable: {e}")
     dist = mlmq.to_numpy(out)
     g.close()
-    return dict(walls=walls, kernel_ms=kms, worker_ms=wms, stats=last, dist=dist, total=total, cfg=cfg)
+    return dict(walls=walls, kernel_ms=kms, worker_ms=wms, stats=last, dist=dist, total=total, cfg=cfg,
+                check_violations=viol, single_pass_ms=statistics.median(pass_ms[1:]) if pass_ms else None)
 
 
 def summarize(name, desc, csr, src, res, cfg):
@@ -110,6 +120,7 @@ def summarize(name, desc, csr, src, res, cfg):
     w_ms = statistics.mean(res["worker_ms"])
     abytes = 12 * m_reach + 32 * n_reach + 4 * csr.n
     st = res["stats"]
+    sp = res["single_pass_ms"]
     return dict(
         workload=name, description=desc, n=csr.n, m=csr.m, source=int(src), n_reach=n_reach, m_reach=m_reach,
         ms_per_step=wall_ms, kernel_ms=k_ms, worker_ms=w_ms,
@@ -117,7 +128,10 @@ def summarize(name, desc, csr, src, res, cfg):
         algorithmic_bytes=abytes, achieved_gbs=abytes / (w_ms * 1e-3) / 1e9,
         work_ratio=st["expansions"] / max(n_reach, 1), edges_scanned=st["edges"], pushes=st["pushes"],
         l2_blocks=st["l2_writes"], hub_chunks=st["hub_chunks"], grid_wgs=st["grid_wgs"],
-        config=cfg.as_dict(),
+        config=cfg.as_dict(), device_check_violations=res["check_violations"],
+        single_pass_ms=sp, single_pass_gedges=(csr.m / sp / 1e6) if sp else None,
+        scan_gedges=st["edges"] / w_ms / 1e6,
+        scan_vs_single_pass=(st["edges"] / w_ms) / (csr.m / sp) if sp else None,
     )
 
 
@@ -350,6 +364,10 @@ def main():
         s = summarize(name, desc, csr, src, res, res["cfg"])
         log(f"[bench] {name}: {s['ms_per_step']:.3f} ms/step wall, kernel {s['kernel_ms']:.3f} ms, "
             f"{s['gteps']:.2f} GTEPS, work ratio {s['work_ratio']:.2f}")
+        if s["single_pass_ms"]:
+            log(f"[bench] {name}: device check {s['device_check_violations']} violations; one sweep of all edges "
+                f"{s['single_pass_ms']:.3f} ms ({s['single_pass_gedges']:.1f} G edges/s), solve scans "
+                f"{s['scan_gedges']:.1f} G edges/s = {s['scan_vs_single_pass']:.2f} of that")
         if not args.no_cpu_baseline:
             cb, ok = cpu_baseline(csr, src, res["dist"])
             s["cpu_baseline"] = cb

@@ -176,6 +176,31 @@ int mlmq_sssp(const mlmq_graph* g, uint32_t source, uint32_t* dist_out, const ml
 int mlmq_bfs(const mlmq_graph* g, uint32_t source, uint32_t* levels_out, const mlmq_config* cfg);
 
 /*
+ * Optimality check of a distance vector on the device. For positive weights a
+ * vector D is the shortest-distance vector from source exactly when
+ *   (1) D[source] == 0;
+ *   (2) for every edge (u, v, w) with D[u] finite, D[v] is finite and
+ *       D[v] <= D[u] + w (evaluated without overflow);
+ *   (3) every other vertex v with D[v] finite has an edge (u, v, w) with
+ *       D[u] + w == D[v]
+ * (by (3) each finite D[v] is the length of a real path, by (1)-(2) no larger
+ * than the shortest one; the definition of the distances of Section 2).
+ * One pass reads every edge word and the labels of both ends, so its time is
+ * also the cost of a single relaxation sweep of the whole graph.
+ * dist: device memory, g's n uint32 (UINT32_MAX = unreachable), only read.
+ * stream: hipStream_t to run on (NULL = null stream); the call blocks until
+ * the check is done. *violations_out (host) receives the number of failed
+ * conditions: each edge failing (2), each vertex failing (3), and 1 if (1)
+ * fails; 0 means D is the exact distance vector. *edge_pass_ms_out (host,
+ * may be NULL) receives the device time of the edge pass. Scratch (n bytes +
+ * a counter) is allocated and freed by the call. MLMQ_ERR_INVALID_ARG for a
+ * NULL argument, source >= n, or a graph with a zero-weight edge (on a cycle
+ * of zero weights, (3) no longer rules out labels that are too small).
+ */
+int mlmq_check(const mlmq_graph* g, uint32_t source, const uint32_t* dist, void* stream, uint64_t* violations_out,
+               float* edge_pass_ms_out);
+
+/*
  * Many queries in one persistent launch. Query i solves graphs[i] from
  * sources[i] into dist_outs[i] (device memory, n_i uint32 each). cfgs may be
  * NULL (per-graph autotuned/default) or hold one config per query; launch

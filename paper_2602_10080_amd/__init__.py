@@ -36,7 +36,7 @@ MEM_HOST, MEM_DEVICE = 0, 1
 # C-ABI entry points declared in include/mlmq.h
 EXPORTS = (
     "mlmq_config_default", "mlmq_graph_create", "mlmq_graph_destroy", "mlmq_graph_info", "mlmq_graph_config",
-    "mlmq_features_host", "mlmq_sssp", "mlmq_bfs", "mlmq_sssp_batch", "mlmq_autotune", "mlmq_server_create",
+    "mlmq_features_host", "mlmq_sssp", "mlmq_bfs", "mlmq_check", "mlmq_sssp_batch", "mlmq_autotune", "mlmq_server_create",
     "mlmq_server_submit", "mlmq_server_poll", "mlmq_server_wait", "mlmq_server_times",
     "mlmq_server_destroy", "mlmq_last_error",
 )
@@ -111,6 +111,7 @@ def _declare(lib):
         "mlmq_features_host": (ctypes.c_int, [i32, i64, vp, vp, vp, ctypes.POINTER(Features)]),
         "mlmq_sssp": (ctypes.c_int, [vp, u32, vp, ctypes.POINTER(Config)]),
         "mlmq_bfs": (ctypes.c_int, [vp, u32, vp, ctypes.POINTER(Config)]),
+        "mlmq_check": (ctypes.c_int, [vp, u32, vp, vp, ctypes.POINTER(u64), ctypes.POINTER(ctypes.c_float)]),
         "mlmq_sssp_batch": (ctypes.c_int, [vp, vp, vp, i32, vp, vp]),
         "mlmq_autotune": (ctypes.c_int, [vp, u32, ctypes.POINTER(Config)]),
         "mlmq_server_create": (ctypes.c_int, [vp, i32, u64, i32, ctypes.POINTER(Config), ctypes.POINTER(vp)]),
@@ -279,6 +280,20 @@ def bfs(graph: Graph, source: int, out=None, config: Optional[Config] = None, st
         config.delta2_log2 = 0
         config.relax_mode = RELAX_PRECHECK
     return _single("mlmq_bfs", graph, source, out, config, stream, stats)
+
+
+def check(graph: Graph, source: int, dist, stream=None):
+    """Optimality check of a device distance vector (mlmq_check): returns
+    (violations, edge_pass_ms); 0 violations = dist is the exact
+    shortest-distance vector from source (positive weights only)."""
+    if not (hasattr(dist, "is_cuda") and dist.is_cuda and dist.numel() == graph.n and dist.element_size() == 4
+            and dist.is_contiguous()):
+        raise ValueError("dist must be a contiguous 4-byte CUDA tensor of n elements")
+    bad = ctypes.c_uint64()
+    ms = ctypes.c_float()
+    _check(lib().mlmq_check(graph.handle, int(source), dist.data_ptr(), _stream_handle(stream), ctypes.byref(bad),
+                            ctypes.byref(ms)))
+    return int(bad.value), float(ms.value)
 
 
 def _single(fn: str, graph: Graph, source: int, out, config: Optional[Config], stream, stats: bool):

@@ -255,9 +255,13 @@ extern "C" int mlmq_graph_create(int32_t n, int64_t m, const int32_t* row_offset
   g->n = n;
   g->m = m;
   compute_features(n, m, hoff, hw, &g->features, g->deg_hist);
-  uint32_t maxw = 0;
-  for (int64_t e = 0; e < m; ++e) maxw = std::max(maxw, hw[e]);
+  uint32_t maxw = 0, minw = kInf;
+  for (int64_t e = 0; e < m; ++e) {
+    maxw = std::max(maxw, hw[e]);
+    minw = std::min(minw, hw[e]);
+  }
   g->max_w = maxw;
+  g->min_w = m ? minw : 1u;
   g->overflow_safe = (uint64_t)(n - 1) * (uint64_t)maxw < (uint64_t)kInf;
   std::vector<uint64_t> adj((size_t)m);
   for (int64_t e = 0; e < m; ++e) adj[e] = (uint32_t)hcol[e] | ((uint64_t)hw[e] << 32);
@@ -865,4 +869,41 @@ extern "C" int mlmq_bfs(const mlmq_graph* g, uint32_t source, uint32_t* levels_o
   tmp.delta2_log2 = 0;
   tmp.relax_mode = MLMQ_RELAX_PRECHECK;
   return run_single(g, source, levels_out, tmp, true);
+}
+
+extern "C" int mlmq_check(const mlmq_graph* g, uint32_t source, const uint32_t* dist, void* stream,
+                          uint64_t* violations_out, float* edge_pass_ms_out) {
+  if (!g) return set_error(MLMQ_ERR_INVALID_ARG, "graph is NULL");
+  if (!dist) return set_error(MLMQ_ERR_INVALID_ARG, "dist is NULL");
+  if (!violations_out) return set_error(MLMQ_ERR_INVALID_ARG, "violations_out is NULL");
+  if (source >= (uint32_t)g->n) return set_error(MLMQ_ERR_INVALID_ARG, "source %u >= n %d", source, g->n);
+  if (g->min_w == 0)
+    return set_error(MLMQ_ERR_INVALID_ARG, "graph has zero-weight edges: the check needs positive weights");
+  int rc = need_device();
+  if (rc) return rc;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const size_t tight_bytes = align_up((size_t)g->n, 256);
+  void* buf = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipError_t e = hipMalloc(&buf, tight_bytes + sizeof(unsigned long long));
+  if (e != hipSuccess) return hip_fail(e, "check scratch");
+  auto* tight = static_cast<uint8_t*>(buf);
+  auto* bad = reinterpret_cast<unsigned long long*>(static_cast<char*>(buf) + tight_bytes);
+  unsigned long long h_bad = 0;
+  float ms = 0.f;
+  e = hipEventCreate(&ev0);
+  if (e == hipSuccess) e = hipEventCreate(&ev1);
+  if (e == hipSuccess) e = hipMemsetAsync(buf, 0, tight_bytes + sizeof(unsigned long long), s);
+  if (e == hipSuccess)
+    e = launch_check(g->d_off, g->d_adj, dist, (uint32_t)g->n, (uint32_t)g->m, source, tight, bad, ev0, ev1, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(&h_bad, bad, sizeof(h_bad), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev0, ev1);
+  if (ev0) (void)hipEventDestroy(ev0);
+  if (ev1) (void)hipEventDestroy(ev1);
+  (void)hipFree(buf);
+  if (e != hipSuccess) return hip_fail(e, "optimality check");
+  *violations_out = h_bad;
+  if (edge_pass_ms_out) *edge_pass_ms_out = ms;
+  return MLMQ_OK;
 }

@@ -20,6 +20,7 @@ struct mlmq_graph {
   mlmq_features features{};
   uint64_t deg_hist[33]{};    // bucket k: degrees in [2^(k-1), 2^k), bucket 0: degree 0
   uint32_t max_w = 0;
+  uint32_t min_w = 0;
   bool overflow_safe = false;  // (n-1) * max_w < 2^32 - 1
   std::mutex mu;
   bool has_tuned = false;

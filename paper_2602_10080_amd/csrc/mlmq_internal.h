@@ -179,6 +179,11 @@ hipError_t launch_server_worker(const ServerArgs& a, uint32_t grid, size_t lds, 
 hipError_t launch_server_admit(const QueryDesc& q, QueryDesc* d_slot, uint64_t* d_join, uint64_t word,
                                uint32_t max_words, hipStream_t s);
 hipError_t launch_server_signal(uint32_t* d_word, uint32_t v, hipStream_t s);
+// Optimality check of a distance vector (edge pass timed between ev0 and ev1,
+// then the vertex pass); tight (n bytes) and *bad must be zero on entry.
+hipError_t launch_check(const int32_t* off, const uint64_t* adj, const uint32_t* dist, uint32_t n, uint32_t m,
+                        uint32_t source, uint8_t* tight, unsigned long long* bad, hipEvent_t ev0, hipEvent_t ev1,
+                        hipStream_t s);
 hipError_t server_occupancy(size_t lds, int* wgs_per_cu);
 
 }  // namespace mlmq

@@ -1292,6 +1292,94 @@ __global__ void mlmq_gather(const QueryDesc* qs, int nq, QueryResult* out) {
   for (int k = 0; k < kNumCounters; ++k) out[i].stats[k] = ctl->stats[k];
 }
 
+// ------------------------------------------------------------ optimality check
+
+// Edges one wave checks per slice; slices are handed out grid-stride.
+constexpr uint32_t kCheckSlice = 4096;
+
+// Largest row q in [lo, n) with off[q] <= y, given off[lo] <= y < off[n]: a
+// 65-way search in which every lane probes one point per round.
+__device__ __forceinline__ uint32_t row_of(const int32_t* off, uint32_t n, uint32_t lo, uint32_t y) {
+  uint32_t hi = n;
+  while (hi - lo > 1u) {
+    const uint32_t span = hi - lo;
+    const uint32_t p = lo + (uint32_t)(((uint64_t)span * (lane() + 1u)) / 65u);  // lo <= p < hi
+    const bool le = (uint32_t)off[p] <= y;
+    const uint64_t ml = ballot(p > lo && le);
+    const uint64_t mg = ballot(p > lo && !le);
+    if (ml) lo = lane_val(p, 63u - (uint32_t)__clzll((long long)ml));
+    if (mg) hi = lane_val(p, first_lane(mg));
+  }
+  return lo;
+}
+
+// Edge pass of the check: for every edge (u, v, w) with dist[u] finite,
+// dist[v] must be finite and at most dist[u] + w; an edge with equality marks
+// v as having a tight in-edge. The lanes of a wave take 64 consecutive edges;
+// their rows come from a window holding the ends of 64 consecutive rows,
+// searched by shuffles and moved forward by row_of when an edge lies past it.
+__global__ void __launch_bounds__(64) mlmq_check_edges(const int32_t* off, const uint64_t* adj, const uint32_t* dist,
+                                                       uint32_t n, uint32_t m, uint8_t* tight,
+                                                       unsigned long long* bad) {
+  const uint32_t nslices = (m + kCheckSlice - 1u) / kCheckSlice;
+  uint32_t nbad = 0;
+  for (uint32_t sl = blockIdx.x; sl < nslices; sl += gridDim.x) {
+    const uint32_t s = sl * kCheckSlice;
+    const uint32_t t = min(m, s + kCheckSlice);
+    uint32_t r = row_of(off, n, 0u, s);
+    uint32_t endk = (uint32_t)off[min(r + lane() + 1u, n)];  // end of row r + lane
+    for (uint32_t x = s; x < t; x += 64u) {
+      const uint32_t e = x + lane();
+      bool todo = e < t;
+      while (ballot(todo)) {
+        // rows of the window that end at or before e; exact while e < end of row r + 63
+        uint32_t j = 0;
+#pragma unroll
+        for (uint32_t st = 32; st; st >>= 1)
+          if ((uint32_t)__shfl(endk, (int)(j + st - 1u)) <= e) j += st;
+        const uint32_t wend = lane_val(endk, 63u);  // end of the window's last row
+        const bool in = todo && e < wend;
+        if (in) {
+          const uint32_t du = dist[r + j];
+          if (du != kInf) {
+            const uint64_t a = adj[e];
+            const uint32_t dv = dist[(uint32_t)a];
+            const uint64_t sum = (uint64_t)du + (a >> 32);
+            if (dv == kInf || (uint64_t)dv > sum)
+              ++nbad;
+            else if ((uint64_t)dv == sum)
+              tight[(uint32_t)a] = 1;
+          }
+          todo = false;
+        }
+        const uint64_t left = ballot(todo);
+        if (left) {
+          r = row_of(off, n, r, lane_val(e, first_lane(left)));
+          endk = (uint32_t)off[min(r + lane() + 1u, n)];
+        }
+      }
+    }
+  }
+  nbad = wave_sum(nbad);
+  if (lane() == 0 && nbad) atomicAdd(bad, (unsigned long long)nbad);
+}
+
+// Vertex pass: dist[source] must be 0, and every other vertex with a finite
+// distance needs a tight in-edge.
+__global__ void __launch_bounds__(256) mlmq_check_vertices(const uint32_t* dist, const uint8_t* tight, uint32_t n,
+                                                           uint32_t source, unsigned long long* bad) {
+  uint32_t nbad = 0;
+  for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+    const uint32_t d = dist[v];
+    if (v == source)
+      nbad += d != 0u;
+    else
+      nbad += (d != kInf && tight[v] == 0);
+  }
+  nbad = wave_sum(nbad);
+  if (lane() == 0 && nbad) atomicAdd(bad, (unsigned long long)nbad);
+}
+
 // ------------------------------------------------------------ host launchers
 
 size_t worker_lds_bytes(uint32_t waves, uint32_t l1_cap, bool two_rings, bool stage) {
@@ -1339,6 +1427,24 @@ hipError_t launch_server_admit(const QueryDesc& q, QueryDesc* d_slot, uint64_t* 
 
 hipError_t launch_server_signal(uint32_t* d_word, uint32_t v, hipStream_t s) {
   hipLaunchKernelGGL(mlmq_server_signal, dim3(1), dim3(64), 0, s, d_word, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_check(const int32_t* off, const uint64_t* adj, const uint32_t* dist, uint32_t n, uint32_t m,
+                        uint32_t source, uint8_t* tight, unsigned long long* bad, hipEvent_t ev0, hipEvent_t ev1,
+                        hipStream_t s) {
+  const uint32_t nslices = (m + kCheckSlice - 1u) / kCheckSlice;
+  const uint32_t grid = nslices < 1u ? 1u : (nslices > 8192u ? 8192u : nslices);
+  hipError_t e = hipEventRecord(ev0, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(mlmq_check_edges, dim3(grid), dim3(64), 0, s, off, adj, dist, n, m, tight, bad);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = hipEventRecord(ev1, s);
+  if (e != hipSuccess) return e;
+  uint32_t vb = (n + 255u) / 256u;
+  vb = vb < 1u ? 1u : (vb > 4096u ? 4096u : vb);
+  hipLaunchKernelGGL(mlmq_check_vertices, dim3(vb), dim3(256), 0, s, dist, tight, n, source, bad);
   return hipGetLastError();
 }
 

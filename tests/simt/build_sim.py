@@ -25,8 +25,19 @@ def transformed_source(checked: bool = False) -> str:
         src = src.replace("c.q.dist + v[u]", "c.q.dist + simt_chk(v[u], c.q.n, \"dist\", __LINE__)")
         src = src.replace("c.q.dist + hv", "c.q.dist + simt_chk(hv, c.q.n, \"dist\", __LINE__)")
         src = src.replace("ld_label(c.q.dist + v)", "ld_label(c.q.dist + simt_chk(v, c.q.n, \"dist\", __LINE__))")
+        # optimality check kernels
+        chk = [("(uint32_t)off[p]", "(uint32_t)off[simt_chk(p, n + 1u, \"off\", __LINE__)]"),
+               ("off[min(r + lane() + 1u, n)]", "off[simt_chk(min(r + lane() + 1u, n), n + 1u, \"off\", __LINE__)]"),
+               ("dist[r + j]", "dist[simt_chk(r + j, n, \"dist\", __LINE__)]"),
+               ("const uint64_t a = adj[e];", "const uint64_t a = adj[simt_chk(e, m, \"adj\", __LINE__)];"),
+               ("dist[(uint32_t)a]", "dist[simt_chk((uint32_t)a, n, \"dist\", __LINE__)]"),
+               ("tight[(uint32_t)a]", "tight[simt_chk((uint32_t)a, n, \"tight\", __LINE__)]"),
+               ("const uint32_t d = dist[v];", "const uint32_t d = dist[simt_chk(v, n, \"dist\", __LINE__)];"),
+               ("tight[v] == 0", "tight[simt_chk(v, n, \"tight\", __LINE__)] == 0")]
+        for a, b in chk:
+            src = src.replace(a, b)
         for pat in ("c.q.adj[eidx]", "c.q.off[lv]", "c.q.dist + lv", "c.q.dist + v[u]", "c.q.dist + hv",
-                    "ld_label(c.q.dist + v)"):
+                    "ld_label(c.q.dist + v)", *[a for a, _ in chk]):
             assert pat in open(KERNEL).read(), pat
     src = src.replace("extern __shared__ uint64_t smem[];",
                       "uint64_t* smem = reinterpret_cast<uint64_t*>(simt::group->lds);")

@@ -176,6 +176,53 @@ extern "C" int sim_sssp(int32_t n, const int32_t* off, const int32_t* col, const
   return 0;
 }
 
+// Runs f on every lane thread of nwg workgroups of `block` lanes.
+template <class F>
+static void run_grid(uint32_t nwg, uint32_t block, F f) {
+  const uint32_t waves = block / 64;
+  std::vector<simt::Wave*> wv;
+  std::vector<simt::Group> grp(nwg);
+  std::vector<std::barrier<>*> bars;
+  for (uint32_t g = 0; g < nwg; ++g) {
+    bars.push_back(new std::barrier<>(block));
+    grp[g].bar = bars.back();
+    grp[g].lds = nullptr;
+    for (uint32_t w2 = 0; w2 < waves; ++w2) wv.push_back(new simt::Wave());
+  }
+  std::vector<std::thread> th;
+  for (uint32_t g = 0; g < nwg; ++g)
+    for (uint32_t t = 0; t < block; ++t)
+      th.emplace_back([&, g, t] {
+        simt::lane = t % 64;
+        simt::nops = 0;
+        simt::wave = wv[g * waves + t / 64];
+        simt::group = &grp[g];
+        simt::tidx = dim3(t);
+        simt::bidx = dim3(g);
+        simt::bdim = dim3(block);
+        simt::gdim = dim3(nwg);
+        f();
+      });
+  for (auto& t : th) t.join();
+  for (auto* p : wv) delete p;
+  for (auto* p : bars) delete p;
+}
+
+// Optimality check: edge pass on nwg one-wave workgroups, then the vertex
+// pass on one 256-lane workgroup; *bad_out receives the violation count.
+extern "C" int sim_check(int32_t n, const int32_t* off, const int32_t* col, const uint32_t* w, uint32_t src,
+                         const uint32_t* dist, uint32_t nwg, uint64_t* bad_out) {
+  const uint32_t m = (uint32_t)off[n];
+  std::vector<uint64_t> adj((size_t)m + 1);
+  for (uint32_t e = 0; e < m; ++e) adj[e] = (uint32_t)col[e] | ((uint64_t)w[e] << 32);
+  std::vector<uint8_t> tight((size_t)n, 0);
+  unsigned long long bad = 0;
+  run_grid(nwg, 64, [&] { mlmq_check_edges(off, adj.data(), dist, (uint32_t)n, m, tight.data(), &bad); });
+  run_grid(1, 256, [&] { mlmq_check_vertices(dist, tight.data(), (uint32_t)n, src, &bad); });
+  *bad_out = bad;
+  return 0;
+}
+
 // Serving form: nq queries (sources srcs[i], outputs dist + i * n) through the
 // resident server kernel with nslots slots and nwg one-wave workgroups. A host
 // driver thread plays the library's admission loop: it resets a query's memory

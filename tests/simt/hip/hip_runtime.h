@@ -30,6 +30,7 @@ struct dim3 {
 };
 typedef int hipError_t;
 typedef void* hipStream_t;
+typedef void* hipEvent_t;
 enum { hipSuccess = 0 };
 
 namespace simt {
@@ -153,6 +154,10 @@ inline uint32_t __builtin_amdgcn_mbcnt_hi(uint32_t m, uint32_t acc) {
 }
 inline int __popcll(unsigned long long m) { return __builtin_popcountll(m); }
 inline int __ffsll(long long m) { return __builtin_ffsll(m); }
+inline int __clzll(long long m) { return m ? __builtin_clzll((unsigned long long)m) : 64; }
+inline unsigned long long atomicAdd(unsigned long long* p, unsigned long long v) {
+  return __atomic_fetch_add(p, v, __ATOMIC_SEQ_CST);
+}
 inline void __syncthreads() { simt::group->bar->arrive_and_wait(); }
 inline void __builtin_amdgcn_wave_barrier() { simt::wave_sync(); }
 #define __builtin_amdgcn_s_sleep(n) std::this_thread::sleep_for(std::chrono::microseconds(4 * (n)))

@@ -92,3 +92,4 @@ def test_device_calls_fail_cleanly_without_gpu():
                                       ctypes.byref(h))
     assert rc == mlmq.ERR_DEVICE and not h
     assert mlmq.lib().mlmq_sssp(None, 0, None, None) == mlmq.ERR_INVALID_ARG
+    assert mlmq.lib().mlmq_check(None, 0, None, None, None, None) == mlmq.ERR_INVALID_ARG

@@ -9,6 +9,7 @@ import pytest
 
 import graphgen as gg
 import oracle
+from check_count import check_count
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -38,6 +39,9 @@ def _solve_and_check(name, csr, src):
     want = oracle.dijkstra(csr, src)
     bad = np.nonzero(got != want)[0]
     assert bad.size == 0, f"{bad.size} mismatches, first {bad[:5]}"
+    nbad, ms = mlmq.check(g, src, out)
+    _say(f"[full] {name}: device check {nbad} violations, edge pass {ms:.3f} ms")
+    assert nbad == 0
     g.close()
 
 
@@ -114,3 +118,22 @@ def test_bfs_rmat23_and_road_grid2048():
         torch.cuda.synchronize()
         assert np.array_equal(mlmq.to_numpy(out), oracle.bfs(csr, src)), name
         g.close()
+
+
+def test_check_perturbed_road_grid2048():
+    """The device check at full size counts the failed conditions of a
+    perturbed vector exactly."""
+    mlmq = _mlmq()
+    csr = gg.grid(2048, 2048, 0.05, seed=1)
+    src = 1024 * 2048 + 1024
+    g = mlmq.Graph.from_csr(csr)
+    want = oracle.dijkstra(csr, src)
+    d = want.copy()
+    rng = np.random.default_rng(3)
+    for v in rng.choice(np.nonzero(want != oracle.UNREACHABLE)[0], 5, replace=False):
+        if v != src:
+            d[v] = np.uint32(int(d[v]) + int(rng.choice([-1, 1])))
+    t = torch.from_numpy(d.view(np.int32)).cuda()
+    nbad, _ = mlmq.check(g, src, t)
+    assert nbad == check_count(csr, src, d) and nbad > 0
+    g.close()

@@ -8,6 +8,7 @@ import pytest
 
 import graphgen as gg
 import oracle
+from check_count import check_count
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -209,3 +210,60 @@ def test_bfs_parity(dev_graphs, graph_name, cfg_name):
     out = mlmq.bfs(g, src, config=cfg)
     torch.cuda.synchronize()
     assert np.array_equal(mlmq.to_numpy(out), oracle.bfs(csr, src))
+
+
+@pytest.mark.parametrize("graph_name", list(GRAPHS))
+def test_check_on_gpu(dev_graphs, oracle_dist, graph_name):
+    """The device optimality check accepts the solve's output, and on perturbed
+    vectors counts exactly the failed conditions; its verdict is the oracle
+    certificate's."""
+    mlmq = _mlmq()
+    g, csr, src = dev_graphs[graph_name]
+    want = oracle_dist[graph_name]
+    _say(f"[check] graph={graph_name}")
+    out = mlmq.sssp(g, src)
+    if csr.m and int(np.min(csr.w)) == 0:
+        with pytest.raises(mlmq.MlmqError) as ei:
+            mlmq.check(g, src, out)
+        assert ei.value.code == mlmq.ERR_INVALID_ARG
+        return
+    bad, ms = mlmq.check(g, src, out)
+    assert bad == 0 and ms >= 0.0
+    rng = np.random.default_rng(17)
+    reach = np.nonzero(want != oracle.UNREACHABLE)[0]
+    reach = reach[reach != src]
+    unreach = np.nonzero(want == oracle.UNREACHABLE)[0]
+    cases = []
+    if reach.size:
+        for delta in (-1, 1):
+            d = want.copy()
+            v = int(rng.choice(reach))
+            d[v] = np.uint32(int(d[v]) + delta)
+            cases.append(d)
+        d = want.copy()
+        d[int(rng.choice(reach))] = oracle.UNREACHABLE
+        cases.append(d)
+    if unreach.size:
+        d = want.copy()
+        d[int(rng.choice(unreach))] = 3
+        cases.append(d)
+    d = want.copy()
+    d[src] = 2
+    cases.append(d)
+    for i, d in enumerate(cases):
+        t = torch.from_numpy(d.view(np.int32)).cuda()
+        bad, _ = mlmq.check(g, src, t)
+        assert bad == check_count(csr, src, d), i
+        code, _, _ = oracle.certificate(csr, src, d)
+        assert (bad == 0) == (code == 0), i
+
+
+def test_check_rejects_zero_weights():
+    mlmq = _mlmq()
+    csr = gg.from_edges(3, [0, 1], [1, 2], [0, 4])
+    g = mlmq.Graph.from_csr(csr)
+    out = mlmq.sssp(g, 0)
+    with pytest.raises(mlmq.MlmqError) as ei:
+        mlmq.check(g, 0, out)
+    assert ei.value.code == mlmq.ERR_INVALID_ARG
+    g.close()

@@ -12,6 +12,7 @@ import pytest
 
 import graphgen as gg
 import oracle
+from check_count import check_count as _check_count
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -124,3 +125,67 @@ def test_bfs_mode_on_cpu_matches_oracle(sim, graph, cfg):
     dist, status, _ = run(sim, csr, src, k)
     assert status[0] == 0
     assert np.array_equal(dist, oracle.bfs(csr, src))
+
+
+# ------------------------------------------------------------ optimality check
+
+def _sim_check(lib, csr, src, d, nwg):
+    off = csr.off32()
+    col = np.ascontiguousarray(csr.col, np.int32)
+    w = np.ascontiguousarray(csr.w, np.uint32)
+    d = np.ascontiguousarray(d, np.uint32)
+    bad = ctypes.c_uint64()
+    vp = ctypes.c_void_p
+    lib.sim_check(ctypes.c_int32(csr.n), vp(off.ctypes.data), vp(col.ctypes.data), vp(w.ctypes.data),
+                  ctypes.c_uint32(src), vp(d.ctypes.data), ctypes.c_uint32(nwg), ctypes.byref(bad))
+    return int(bad.value)
+
+
+def _check_graphs():
+    rng = np.random.default_rng(5)
+    # a star whose centre row spans three 4096-edge slices, plus isolated vertices between rows
+    n = 9000
+    centre = np.zeros(8500, int)
+    leaves = rng.choice(np.arange(1, n), 8500, replace=False)
+    star = gg.from_edges(n, np.concatenate([centre, leaves]), np.concatenate([leaves, centre]),
+                         rng.integers(1, 40, 17000))
+    return {"grid16": (gg.grid(16, 16, 0.0, seed=1), 0), "road24": (gg.grid(24, 20, 0.1, seed=2), 77),
+            "rmat10": (lambda g: (g, gg.max_degree_vertex(g)))(gg.rmat(10, 8, seed=3)),
+            "star": (star, 0), "hubs": (_hubs(), 0),
+            "edgeless": (gg.from_edges(5, [], [], []), 2)}
+
+
+@pytest.mark.parametrize("graph", ["grid16", "road24", "rmat10", "star", "hubs", "edgeless"])
+def test_check_kernel_on_cpu(sim, graph):
+    """The check accepts the oracle's distances and rejects perturbed vectors;
+    its count equals the conditions counted directly, its verdict equals the
+    oracle's certificate."""
+    csr, src = _check_graphs()[graph]
+    want = oracle.dijkstra(csr, src)
+    rng = np.random.default_rng(11)
+    reach = np.nonzero(want != oracle.UNREACHABLE)[0]
+    unreach = np.nonzero(want == oracle.UNREACHABLE)[0]
+    cases = [want.copy()]
+    for _ in range(1):
+        if reach.size > 1:
+            for delta in (-1, 1):
+                d = want.copy()
+                v = int(rng.choice(reach[reach != src]))
+                d[v] = np.uint32(int(d[v]) + delta)
+                cases.append(d)
+            d = want.copy()
+            d[int(rng.choice(reach[reach != src]))] = oracle.UNREACHABLE
+            cases.append(d)
+        if unreach.size:
+            d = want.copy()
+            d[int(rng.choice(unreach))] = 5
+            cases.append(d)
+    d = want.copy()
+    d[src] = 1
+    cases.append(d)
+    for i, d in enumerate(cases):
+        for nwg in ((1, 3) if i == 0 else (3,)):
+            got = _sim_check(sim, csr, src, d, nwg)
+            assert got == _check_count(csr, src, d), (i, nwg)
+            code, _, _ = oracle.certificate(csr, src, d)
+            assert (got == 0) == (code == 0), (i, nwg, got, code)
