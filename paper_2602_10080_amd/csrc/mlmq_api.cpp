@@ -704,7 +704,7 @@ void heuristic_config(const mlmq_graph* g, mlmq_config* c) {
     const double m = f.nnz;
     c->th_hub = m < 64e6 ? 8192 : 16384;
     c->hub_chunk = 4096;
-    c->l1_cap = m < 64e6 ? 128 : (m < 192e6 ? 256 : 512);
+    c->l1_cap = m < 64e6 ? 128 : 256;
     const uint32_t cus = (uint32_t)std::max(1, device_info()->cus);
     c->grid_wgs = (uint32_t)std::min<double>(6.0 * cus, std::max(512.0, m / 32768.0));
     return;
