@@ -153,6 +153,25 @@ def bench_bfs(mlmq, torch, csr, src, steps=5):
     return dict(worker_ms=w, gteps_device=m_reach / w / 1e6, work_ratio=st["expansions"] / max(1, reach(csr, mlmq.to_numpy(out))[0]))
 
 
+def stream_probe(torch, nbytes=1 << 30, reps=5):
+    """Achievable device bandwidth: a plain 1 GiB device-to-device copy (one
+    read and one write of every byte), timed with events on the stream."""
+    src = torch.empty(nbytes // 4, dtype=torch.int32, device="cuda").fill_(1)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return 2 * nbytes / ms / 1e6
+
+
 def cpu_baseline(csr, src, gpu_dist, max_seconds=30.0):
     """Oracle Dijkstra on one core; repeated while under the time bound."""
     import oracle
@@ -380,6 +399,10 @@ def main():
             primary = s
         del csr, res
 
+    stream_gbs = stream_probe(torch)
+    log(f"[bench] stream probe (1 GiB device copy): {stream_gbs:.0f} GB/s")
+    for s in results.values():
+        s["achieved_vs_stream"] = s["achieved_gbs"] / stream_gbs
     batch = bench_batch(mlmq, torch, args.tune_ms) if args.batch else None
     serving = bench_serve(mlmq, torch, args.serve, args.serve_load, args.serve_budget_gb) if args.serve else None
 
@@ -403,6 +426,8 @@ def main():
                      "frac": p["achieved_gbs"] / HBM_PEAK_GBS, "traffic": measured_traffic(p["workload"])},
         "cpu_baseline": p.get("cpu_baseline"),
         "verified_against_oracle": p.get("verified_against_oracle"),
+        "device_check_violations": p.get("device_check_violations"),
+        "stream_probe": {"gbs": stream_gbs, "what": "1 GiB device-to-device copy, read + write bytes / event time"},
         "batch": batch,
         "serving": serving,
         "detail": {k: {kk: vv for kk, vv in v.items() if kk not in ("config",)} for k, v in results.items()},

@@ -222,9 +222,9 @@ int mlmq_autotune(mlmq_graph* g, uint32_t budget_ms, mlmq_config* out);
 /*
  * Continuous-batching server over resident graphs (the serving form of the
  * Section 4.1 persistent kernel): a resident kernel picks up queries from a
- * table of max_slots (1..64) slots while others run; its idle waves sleep and
- * leave after a stretch without work, and the library relaunches it when work
- * arrives. Queries are admitted in arrival order when a slot is free and their
+ * table of max_slots (1..64) slots while others run; its idle waves sleep, the
+ * library stops the whole kernel after 200 ms with no query pending or running
+ * and relaunches it when work arrives. Queries are admitted in arrival order when a slot is free and their
  * state (queues + n distances) fits in mem_budget_bytes; a query larger than
  * the budget runs alone. Each graph uses cfg if given, else its own config
  * (mlmq_graph_config); graphs must outlive the server. submit never blocks

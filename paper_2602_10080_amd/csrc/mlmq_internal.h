@@ -127,8 +127,9 @@ struct LaunchArgs {
 
 // Control words of a resident server kernel (device memory).
 struct ServerCtrl {
-  Word stop;    // 1: idle waves leave the kernel
-  Word cancel;  // 1: every query stops (status canceled)
+  Word stop;       // 1: idle waves leave the kernel
+  Word cancel;     // 1: every query stops (status canceled)
+  Word last_busy;  // low 32 bits of the wall clock when a wave last joined or left a query
 };
 
 struct ServerArgs {

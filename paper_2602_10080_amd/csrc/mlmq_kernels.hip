@@ -1177,6 +1177,8 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) ml
       }
       if (!lane_val(won, 0)) continue;
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      const uint32_t t_join = (uint32_t)wall_clock64();  // read by the whole wave
+      if (l == 0) st32(&a.ctl->last_busy.v, t_join);
       const QueryDesc q = load_desc_coherent(a.slots + s);
       Ctx c;
       setup_ctx(c, q, smem, a.l1_cap, a.l1_two, a.stage, &a.ctl->cancel.v, (uint64_t)wall_clock64() + a.timeout_ticks,
@@ -1198,11 +1200,16 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) ml
         }
       }
       last_busy = (uint64_t)wall_clock64();
+      if (l == 0) st32(&a.ctl->last_busy.v, (uint32_t)last_busy);
       idle = 0;
       continue;
     }
     if (uni(ld32(&a.ctl->stop.v))) break;
-    if ((uint64_t)wall_clock64() - last_busy > a.idle_exit_ticks) break;
+    // failsafe exit, measured from the last query activity of any wave so that
+    // the waves leave together (the host stops an idle server much earlier)
+    const uint32_t now = (uint32_t)wall_clock64();
+    const uint32_t since = min(now - (uint32_t)last_busy, now - uni(ld32(&a.ctl->last_busy.v)));
+    if (since > a.idle_exit_ticks) break;
     ++idle;
     backoff(min(idle >> 2, 6u));
     // long-idle waves poll the slot table less often (up to ~50 us apart)

@@ -138,6 +138,8 @@ struct mlmq_server {
   uint64_t quit_ns = 0;
   bool cancel_sent = false;
   bool leak = false;  // the device never let go of the server's memory
+  bool stopping = false;        // stop flag raised on an idle server, kernel not yet gone
+  uint64_t last_active_ns = 0;  // last time a query was pending or running
 };
 
 namespace {
@@ -295,13 +297,41 @@ hipError_t keep_alive(mlmq_server* s) {
   return launch_server_worker(s->args, s->grid, s->lds, s->ws);
 }
 
+// The resident kernel leaves as a whole: after kIdleStopNs without pending
+// or running queries the host raises the stop flag and admits nothing until
+// the kernel is gone; the flag is cleared on the worker stream, ahead of the
+// next launch. (Waves leaving one by one would leave a thin kernel that the
+// host does not relaunch, and later queries would run on a few waves.)
+constexpr uint64_t kIdleStopNs = 200ull * 1000000ull;
+
+hipError_t idle_stop(mlmq_server* s) {
+  const uint64_t now = now_ns();
+  const bool quiet = !in_flight(s) && s->pending.empty();
+  if (!quiet || !s->last_active_ns) s->last_active_ns = now;
+  if (!s->stopping && quiet && now - s->last_active_ns > kIdleStopNs && hipStreamQuery(s->ws) == hipErrorNotReady) {
+    const hipError_t e = launch_server_signal(&s->d_ctl->stop.v, 1u, s->cs);
+    if (e != hipSuccess) return e;
+    s->stopping = true;
+  }
+  if (s->stopping && hipStreamQuery(s->ws) == hipSuccess) {
+    const hipError_t e = launch_server_signal(&s->d_ctl->stop.v, 0u, s->ws);
+    if (e != hipSuccess) return e;
+    s->stopping = false;
+  }
+  return hipSuccess;
+}
+
 void server_loop(mlmq_server* s) {
   (void)hipSetDevice(device_info()->device);
   std::unique_lock<std::mutex> lk(s->mu);
   for (;;) {
     std::string err;
     bool any = collect(s);
-    if (!s->quit) any |= admit(s, &err);
+    if (!s->quit) {
+      const hipError_t ie = idle_stop(s);
+      if (ie != hipSuccess) err = std::string("idle stop: ") + hipGetErrorString(ie);
+      if (err.empty() && !s->stopping) any |= admit(s, &err);
+    }
     hipError_t e = err.empty() ? keep_alive(s) : hipErrorUnknown;
     if (e != hipSuccess) {
       s->fatal = err.empty() ? std::string("resident kernel: ") + hipGetErrorString(e) : err;
@@ -431,7 +461,7 @@ int mlmq_server_create(const mlmq_graph* const* graphs, int32_t ngraphs, uint64_
   s->timeout_ms = timeout_ms ? timeout_ms : 60000;
   a.timeout_ticks = (uint64_t)s->timeout_ms * di->ticks_per_ms;
   a.cap_wait_ticks = 20ull * di->ticks_per_ms;
-  a.idle_exit_ticks = 200ull * di->ticks_per_ms;
+  a.idle_exit_ticks = 2000ull * di->ticks_per_ms;  // failsafe; the host stops an idle server after 200 ms
   s->th = std::thread(server_loop, s);
   *out = s;
   return MLMQ_OK;
