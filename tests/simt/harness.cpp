@@ -208,6 +208,79 @@ static void run_grid(uint32_t nwg, uint32_t block, F f) {
   for (auto* p : bars) delete p;
 }
 
+// The queue-unit example: distances 5, 1, 2 written to one wave's L1 one at a
+// time (vertices 0, 1, 2), then one L1 read. read_d receives the distances
+// read, in lane order (*nread of them); left_d what stays in L1 (near ring,
+// then far ring); l2_d what went to the global level (ring 0, block 0).
+extern "C" int sim_l1_example(uint32_t l1_type, uint32_t delta1, uint32_t* read_d, uint32_t* nread, uint32_t* left_d,
+                              uint32_t* nleft, uint32_t* l2_d, uint32_t* nl2) {
+  const uint32_t nb_log2 = 4, cap = 64;
+  QueryCtrl* ctrl = zalloc<QueryCtrl>(1);
+  RingCtr* rings = zalloc<RingCtr>(1);
+  uint64_t* hdr = zalloc<uint64_t>(1u << nb_log2);
+  uint64_t* data = zalloc<uint64_t>((1u << nb_log2) * 64);
+  uint32_t dist[3] = {kInf, kInf, kInf};
+  // what the init kernel would leave: empty counters, every L2 slot free for lap 0
+  std::memset(ctrl, 0, sizeof(QueryCtrl));
+  std::memset(rings, 0, sizeof(RingCtr));
+  std::memset(hdr, 0, sizeof(uint64_t) << nb_log2);
+  QueryDesc* q = zalloc<QueryDesc>(1);
+  std::memset(q, 0, sizeof(QueryDesc));
+  q->dist = dist;
+  q->ctrl = ctrl;
+  q->rings = rings;
+  q->hdr = hdr;
+  q->data = data;
+  q->n = 3;
+  q->nb_log2 = nb_log2;
+  q->nrings = 1;
+  q->hub_cap = 1;
+  q->l1_type = l1_type;
+  q->l2_type = MLMQ_L2_FIFO;
+  q->l1_cap = cap;
+  q->delta1 = delta1;
+  q->bnum = 1;
+  q->th_v = 32;
+  q->want_wgs = 1;
+  const bool two = l1_type == MLMQ_L1_NEARFAR;
+  uint8_t* lds = zalloc<uint8_t>(worker_lds_bytes(1, cap, two, false));
+  uint32_t cancel = 0;
+  run_grid(1, 64, [&] {
+    simt::group->lds = lds;
+    Ctx c;
+    setup_ctx(c, *q, reinterpret_cast<uint64_t*>(lds), cap, two ? 1u : 0u, 0u, &cancel, ~0ull >> 1, 1000000ull,
+              nullptr);
+    const uint32_t ds[3] = {5, 1, 2};
+    for (uint32_t i = 0; i < 3; ++i) write_l1(c, make_elem(i, ds[i]), lane() == 0);
+    uint64_t e = 0;
+    bool ok = false;
+    l1_take(c, e, ok);
+    const uint32_t k = popc(ballot(ok));
+    if (ok) read_d[lane()] = elem_d(e);
+    if (lane() == 0) {
+      *nread = k;
+      uint32_t j = 0;
+      for (uint32_t x = c.qh; x != c.qt; ++x) left_d[j++] = elem_d(c.l1[x & c.l1mask]);
+      for (uint32_t x = c.fh; x != c.ft; ++x) left_d[j++] = elem_d(c.far[x & c.l1mask]);
+      *nleft = j;
+    }
+  });
+  // a written L2 block: its header holds the element count, data the elements
+  uint32_t j = 0;
+  if (rings[0].tail.v) {
+    const uint32_t cnt = (uint32_t)hdr[0];  // low half: element count; high half: lap state
+    for (uint32_t x = 0; x < cnt && x < 64; ++x) l2_d[j++] = (uint32_t)(data[x] >> 32);
+  }
+  *nl2 = j;
+  free(ctrl);
+  free(rings);
+  free(hdr);
+  free(data);
+  free(q);
+  free(lds);
+  return 0;
+}
+
 // Optimality check: edge pass on nwg one-wave workgroups, then the vertex
 // pass on one 256-lane workgroup; *bad_out receives the violation count.
 extern "C" int sim_check(int32_t n, const int32_t* off, const int32_t* col, const uint32_t* w, uint32_t src,

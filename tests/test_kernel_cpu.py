@@ -189,3 +189,29 @@ def test_check_kernel_on_cpu(sim, graph):
             assert got == _check_count(csr, src, d), (i, nwg)
             code, _, _ = oracle.certificate(csr, src, d)
             assert (got == 0) == (code == 0), (i, nwg, got, code)
+
+
+# ------------------------------------------------------------ queue-unit example
+
+@pytest.mark.parametrize("l1_type,delta1,read,left,l2", [
+    # vector: FIFO, the first two read are {5, 1}
+    (1, 64, [5, 1, 2], [], []),
+    # near-far: NF = min of the first batch + delta1 = 3, so {1, 2} near and 5 kept far
+    (2, 2, [1, 2], [5], []),
+    # filter: F = 3, so {1, 2} kept and 5 sent to the global level
+    (3, 3, [1, 2], [], [5]),
+    # Small-Label-First deque: 5; 1 in front of 5; 2 behind: [1, 5, 2]
+    (4, 64, [1, 5, 2], [], []),
+])
+def test_queue_unit_example(sim, l1_type, delta1, read, left, l2):
+    """Section 3.4's queue example (its figure is missing from the text, so
+    this pins our reading): distances 5, 1, 2 written one at a time to a
+    wave's L1, then one L1 read, for each L1 policy of the kernel."""
+    rd, lf, l2d = (np.zeros(64, np.uint32) for _ in range(3))
+    nr, nl, n2 = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
+    vp = ctypes.c_void_p
+    sim.sim_l1_example(ctypes.c_uint32(l1_type), ctypes.c_uint32(delta1), vp(rd.ctypes.data), ctypes.byref(nr),
+                       vp(lf.ctypes.data), ctypes.byref(nl), vp(l2d.ctypes.data), ctypes.byref(n2))
+    assert list(rd[:nr.value]) == read
+    assert list(lf[:nl.value]) == left
+    assert list(l2d[:n2.value]) == l2
