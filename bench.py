@@ -146,11 +146,14 @@ def bench_bfs(mlmq, torch, csr, src, steps=5):
         _, st = mlmq.bfs(g, src, out=out, stats=True)
         wms.append(st["worker_ms"])
     torch.cuda.synchronize()
-    _, m_reach = reach(csr, mlmq.to_numpy(out))
+    lv = mlmq.to_numpy(out)
+    n_reach, m_reach = reach(csr, lv)
     g.close()
     w = statistics.median(wms)
-    log(f"[bench] bfs: {w:.2f} ms, {m_reach / w / 1e6:.2f} GTEPS")
-    return dict(worker_ms=w, gteps_device=m_reach / w / 1e6, work_ratio=st["expansions"] / max(1, reach(csr, mlmq.to_numpy(out))[0]))
+    levels = int(lv[lv != INF].max()) + 1
+    log(f"[bench] bfs: {w:.2f} ms, {m_reach / w / 1e6:.2f} GTEPS, {levels} levels, {w / levels * 1e3:.2f} us per level")
+    return dict(worker_ms=w, gteps_device=m_reach / w / 1e6, work_ratio=st["expansions"] / max(1, n_reach),
+                levels=levels, us_per_level=w / levels * 1e3)
 
 
 def stream_probe(torch, nbytes=1 << 30, reps=5):
@@ -182,9 +185,12 @@ def cpu_baseline(csr, src, gpu_dist, max_seconds=30.0):
         times.append(time.perf_counter() - t0)
     _, m_reach = reach(csr, want)
     t = statistics.median(times)
+    # the oracle's certificate of the GPU vector also gives the fewest-hop
+    # depth of the shortest-path DAG (for the latency floor)
+    code, _, depth = oracle.certificate(csr, src, gpu_dist)
     return dict(value=m_reach / t / 1e9, unit="GTEPS", cores=1, kind="oracle",
                 sample=f"{len(times)} full single-source solve(s), median {t:.2f} s",
-                seconds=t), bool(np.array_equal(want, gpu_dist))
+                seconds=t, sp_depth=int(depth) if code == 0 else None), bool(np.array_equal(want, gpu_dist))
 
 
 def bench_batch(mlmq, torch, tune_ms, nrmat=256, ngrid=64):
@@ -394,6 +400,18 @@ def main():
             log(f"[bench] {name}: oracle {cb['seconds']:.2f} s ({cb['value']:.4f} GTEPS), match={ok}")
         if name in ("rmat23", "grid2048"):
             s["bfs"] = bench_bfs(mlmq, torch, csr, src)
+            depth = s.get("cpu_baseline", {}).get("sp_depth")
+            if depth is not None and name.startswith("grid"):
+                # latency floor of a high-diameter graph: fewest-hop depth of the
+                # shortest-path DAG x the per-level time of the breadth-first run
+                # on the same queues (on power-law graphs a level is throughput-
+                # bound, not a round trip, and the floor says nothing)
+                floor = (depth + 1) * s["bfs"]["us_per_level"] / 1e3
+                s["sp_depth"] = int(depth)
+                s["latency_floor_ms"] = floor
+                s["vs_latency_floor"] = s["worker_ms"] / floor
+                log(f"[bench] {name}: shortest-path depth {depth} hops; latency floor {floor:.2f} ms; "
+                    f"solve = {s['vs_latency_floor']:.2f} x floor")
         results[name] = s
         if i == 0:
             primary = s
