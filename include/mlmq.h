@@ -171,7 +171,8 @@ int mlmq_sssp(const mlmq_graph* g, uint32_t source, uint32_t* dist_out, const ml
  * study): levels_out[v] = fewest edges on a path from source, MLMQ_UNREACHABLE
  * where none; the weights of g are ignored. Buffers, streams and errors as for
  * mlmq_sssp. cfg NULL = the graph's config with its near-far window set to one
- * level and its bucket width to 1.
+ * level and its bucket width to 1 (its relax mode kept: atomicMin alone on
+ * low-degree graphs, with the label pre-check on power-law graphs).
  */
 int mlmq_bfs(const mlmq_graph* g, uint32_t source, uint32_t* levels_out, const mlmq_config* cfg);
 

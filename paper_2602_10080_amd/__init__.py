@@ -278,7 +278,6 @@ def bfs(graph: Graph, source: int, out=None, config: Optional[Config] = None, st
         config = graph.config()
         config.delta1 = 1
         config.delta2_log2 = 0
-        config.relax_mode = RELAX_PRECHECK
     return _single("mlmq_bfs", graph, source, out, config, stream, stats)
 
 

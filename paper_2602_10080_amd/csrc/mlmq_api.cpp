@@ -867,7 +867,6 @@ extern "C" int mlmq_bfs(const mlmq_graph* g, uint32_t source, uint32_t* levels_o
   tmp = *resolve_config(g, nullptr, &tmp);
   tmp.delta1 = 1;
   tmp.delta2_log2 = 0;
-  tmp.relax_mode = MLMQ_RELAX_PRECHECK;
   return run_single(g, source, levels_out, tmp, true);
 }
 
