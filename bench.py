@@ -356,9 +356,8 @@ def main():
                     help="only run a plain device copy of this many MiB three times (calibrates HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
-              "(the single-source solve runs on one device; see DESIGN.md for how it would shard)",
-              file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              "(the single-source solve runs on one device)", file=sys.stderr)
         sys.exit(2)
 
     import torch
