@@ -98,6 +98,14 @@ def measure(mlmq, torch, csr, src, overrides, steps, warmup):
         wms.append(st["worker_ms"])
         last = st
     total = time.perf_counter() - t_all
+    # the same solve into a host buffer: the library copies the distances back
+    # (PCIe-inclusive time; never the headline value)
+    host_out = np.empty(csr.n, np.uint32)
+    host_ms = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        mlmq.sssp(g, src, out=host_out, config=cfg, stream=stream)
+        host_ms.append((time.perf_counter() - t0) * 1e3)
     # device optimality check of the output; its edge pass (every edge word and
     # both labels read once) is the cost of one relaxation sweep of the graph
     viol, pass_ms = None, []
@@ -109,7 +117,10 @@ def measure(mlmq, torch, csr, src, overrides, steps, warmup):
         log(f"[bench] device check unavailable: {e}")
     dist = mlmq.to_numpy(out)
     g.close()
+    if not np.array_equal(host_out, dist):
+        raise SystemExit("host-output solve differs from the device-output solve")
     return dict(walls=walls, kernel_ms=kms, worker_ms=wms, stats=last, dist=dist, total=total, cfg=cfg,
+                host_output_ms=statistics.median(host_ms),
                 check_violations=viol, single_pass_ms=statistics.median(pass_ms[1:]) if pass_ms else None)
 
 
@@ -125,6 +136,8 @@ def summarize(name, desc, csr, src, res, cfg):
         workload=name, description=desc, n=csr.n, m=csr.m, source=int(src), n_reach=n_reach, m_reach=m_reach,
         ms_per_step=wall_ms, kernel_ms=k_ms, worker_ms=w_ms,
         gteps=m_reach / (wall_ms * 1e-3) / 1e9, gteps_device=m_reach / (k_ms * 1e-3) / 1e9,
+        gteps_undirected=m_reach / 2 / (wall_ms * 1e-3) / 1e9,
+        ms_host_output=res["host_output_ms"],
         algorithmic_bytes=abytes, achieved_gbs=abytes / (w_ms * 1e-3) / 1e9,
         work_ratio=st["expansions"] / max(n_reach, 1), edges_scanned=st["edges"], pushes=st["pushes"],
         l2_blocks=st["l2_writes"], hub_chunks=st["hub_chunks"], grid_wgs=st["grid_wgs"],
