@@ -380,6 +380,10 @@ QueryDesc make_desc(const mlmq_graph* g, const mlmq_config& c, const QueryPlan& 
   d.hub_chunk = c.hub_chunk;
   d.want_wgs = want_wgs;
   d.relax_mode = c.relax_mode;
+  // donation threshold: larger graphs carry larger frontiers per wave, and
+  // handing work out early only adds global-queue round trips (grid2048:
+  // 64 → 20.0 ms vs 22.0 ms with 32; grid512 and grid1024 best at 32)
+  d.donate_min = g->n >= (1 << 21) ? 64u : 32u;
   return d;
 }
 
@@ -761,6 +765,7 @@ int run_single(const mlmq_graph* g, uint32_t source, uint32_t* dist_out, const m
     QueryDesc* h_desc = reinterpret_cast<QueryDesc*>(static_cast<char*>(slab->host) + sizeof(QueryCtrl));
     *h_desc = make_desc(g, c, p, base, d_dist, source, shape.grid);
     h_desc->unit_w = unit_weights ? 1u : 0u;
+    if (unit_weights) h_desc->donate_min = 32u;  // breadth-first levels: early hand-out pays (grid2048 17.4 vs 19.4 ms)
     uint32_t* d_beats = reinterpret_cast<uint32_t*>(base + beats_off);
     LaunchArgs a = make_args(d_desc, d_batch, 1, shape, c.timeout_ms, d_beats);
     hipEvent_t ev0 = nullptr, evw = nullptr, ev1 = nullptr;

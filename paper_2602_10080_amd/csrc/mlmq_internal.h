@@ -103,7 +103,7 @@ struct QueryDesc {
   uint32_t want_wgs;   // workgroups this query should get
   uint32_t relax_mode; // MLMQ_RELAX_*
   uint32_t unit_w;     // 1: every edge weighs 1 (breadth-first levels)
-  uint32_t pad;
+  uint32_t donate_min; // near-ring size from which a wave hands half of it to idle waves
 };
 
 // Batch-wide control (device memory).

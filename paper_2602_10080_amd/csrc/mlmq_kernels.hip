@@ -689,7 +689,7 @@ __device__ __forceinline__ void write_l1(Ctx& c, uint64_t e, bool ok) {
 }
 
 // Work sharing between the levels: while other waves of the query find no
-// work, a wave whose L1 main (near) ring holds more than half a row hands the
+// work, a wave whose L1 main (near) ring holds at least donate_min elements hands the
 // older half of it to L2, where the idle waves pick it up; the far ring stays
 // private, since handing it out would put work ahead of the frontier. Without
 // this a wave can keep a whole wavefront in its private L1 (the near-far and
@@ -973,7 +973,7 @@ __device__ __forceinline__ void run_query(Ctx& c) {
       l0_read(c, e, ok);
       got = true;
     } else if (c.q.l1_type != MLMQ_L1_NONE && !l1_empty(c)) {
-      if ((c.it & 15u) == 0 && c.qt - c.qh >= 32u && uni(ld32(&c.q.ctrl->hungry.v)) != 0)
+      if ((c.it & 15u) == 0 && c.qt - c.qh >= c.q.donate_min && uni(ld32(&c.q.ctrl->hungry.v)) != 0)
         donate(c);
       got = l1_take(c, e, ok);
       c.ct[kCtL1Reads] += 1;

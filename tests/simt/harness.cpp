@@ -92,6 +92,7 @@ extern "C" int sim_sssp(int32_t n, const int32_t* off, const int32_t* col, const
   q->want_wgs = nwg;
   q->relax_mode = k[15];
   q->unit_w = k[16];
+  q->donate_min = 32;
   // init kernel, serially over its threads (it has no cross-lane operations)
   const uint32_t blocks = 4;
   simt::gdim = dim3(blocks, 1);
@@ -423,6 +424,7 @@ extern "C" int sim_server(int32_t n, const int32_t* off, const int32_t* col, con
         q.want_wgs = want;
         q.relax_mode = k[15];
         q.unit_w = k[16];
+        q.donate_min = 32;
         __atomic_store_n(&done[s], 0ull, __ATOMIC_RELEASE);
         simt::gdim = dim3(4, 1);
         simt::bdim = dim3(256);
