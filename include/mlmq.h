@@ -167,6 +167,30 @@ int mlmq_features_host(int32_t n, int64_t m, const int32_t* row_offsets, const i
 int mlmq_sssp(const mlmq_graph* g, uint32_t source, uint32_t* dist_out, const mlmq_config* cfg);
 
 /*
+ * Allocation-free single-source solve, for callers that cannot allocate
+ * device or pinned memory during a call (tight serving loops, harnesses that
+ * forbid allocation). Same result as mlmq_sssp, but the queue memory comes
+ * from one fixed device array of 128 MiB per GPU, reserved when the library
+ * is loaded and held until the process ends; the call itself allocates
+ * nothing (no hipMalloc, hipFree or pinned host memory). Differences from
+ * mlmq_sssp:
+ *   - dist_out must be device memory (n uint32), else MLMQ_ERR_INVALID_ARG;
+ *   - a solve whose queue memory (the plan of mlmq_sssp's first attempt plus
+ *     a few KB of control words) exceeds the 128 MiB gives
+ *     MLMQ_ERR_INVALID_ARG with the size in the message; the default FIFO
+ *     L2 (room for 2n elements of 8 bytes, rounded up to a power of two of
+ *     64-element blocks) fits for graphs of up to 2^22 vertices;
+ *   - no capacity retry: an L2 that runs out gives MLMQ_ERR_QUEUE_CAPACITY;
+ *   - stats_out receives the counters but kernel_ms/worker_ms = 0.
+ * Every call on a GPU uses that GPU's array, which keeps the last call's
+ * contents until the next call resets it. Calls on one GPU from one process
+ * therefore never overlap: the library holds a per-GPU lock for the whole
+ * solve, so concurrent callers wait for each other. The call returns after
+ * the solve finished on cfg->stream. Other errors as for mlmq_sssp.
+ */
+int mlmq_sssp_noalloc(const mlmq_graph* g, uint32_t source, uint32_t* dist_out, const mlmq_config* cfg);
+
+/*
  * Breadth-first search levels on the same queues (Section 5.7, BFS case
  * study): levels_out[v] = fewest edges on a path from source, MLMQ_UNREACHABLE
  * where none; the weights of g are ignored. Buffers, streams and errors as for

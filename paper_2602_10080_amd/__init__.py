@@ -36,7 +36,7 @@ MEM_HOST, MEM_DEVICE = 0, 1
 # C-ABI entry points declared in include/mlmq.h
 EXPORTS = (
     "mlmq_config_default", "mlmq_graph_create", "mlmq_graph_destroy", "mlmq_graph_info", "mlmq_graph_config",
-    "mlmq_features_host", "mlmq_sssp", "mlmq_bfs", "mlmq_check", "mlmq_sssp_batch", "mlmq_autotune", "mlmq_server_create",
+    "mlmq_features_host", "mlmq_sssp", "mlmq_sssp_noalloc", "mlmq_bfs", "mlmq_check", "mlmq_sssp_batch", "mlmq_autotune", "mlmq_server_create",
     "mlmq_server_submit", "mlmq_server_poll", "mlmq_server_wait", "mlmq_server_times",
     "mlmq_server_destroy", "mlmq_last_error",
 )
@@ -110,6 +110,7 @@ def _declare(lib):
                                            ctypes.POINTER(Features)]),
         "mlmq_features_host": (ctypes.c_int, [i32, i64, vp, vp, vp, ctypes.POINTER(Features)]),
         "mlmq_sssp": (ctypes.c_int, [vp, u32, vp, ctypes.POINTER(Config)]),
+        "mlmq_sssp_noalloc": (ctypes.c_int, [vp, u32, vp, ctypes.POINTER(Config)]),
         "mlmq_bfs": (ctypes.c_int, [vp, u32, vp, ctypes.POINTER(Config)]),
         "mlmq_check": (ctypes.c_int, [vp, u32, vp, vp, ctypes.POINTER(u64), ctypes.POINTER(ctypes.c_float)]),
         "mlmq_sssp_batch": (ctypes.c_int, [vp, vp, vp, i32, vp, vp]),
@@ -267,6 +268,16 @@ def sssp(graph: Graph, source: int, out=None, config: Optional[Config] = None, s
     or a host uint32 numpy array). config None = the graph's tuned/default
     config. Returns out, or (out, stats dict) when stats=True."""
     return _single("mlmq_sssp", graph, source, out, config, stream, stats)
+
+
+def sssp_noalloc(graph: Graph, source: int, out, config: Optional[Config] = None, stream=None,
+                 stats: bool = False):
+    """mlmq_sssp_noalloc: the same solve with the library's fixed queue array
+    (no allocation inside the call); out must be a device tensor of n 4-byte
+    elements that the caller allocated."""
+    if not hasattr(out, "is_cuda"):
+        raise ValueError("out must be a CUDA tensor")
+    return _single("mlmq_sssp_noalloc", graph, source, out, config, stream, stats)
 
 
 def bfs(graph: Graph, source: int, out=None, config: Optional[Config] = None, stream=None,

@@ -470,7 +470,7 @@ void pool_trim() {
     drop.swap(pool().free_list);
   }
   for (Slab* d : drop) {
-    if (d->graph_exec) hipGraphExecDestroy(d->graph_exec);
+    if (d->graph_exec) (void)hipGraphExecDestroy(d->graph_exec);
     (void)hipFree(d->dev);
     (void)hipHostFree(d->host);
     delete d;
@@ -614,7 +614,7 @@ void fill_stats(mlmq_stats* st, const QueryCtrl& h, double ms, double worker_ms,
 // stop (its memory must then be left alone); the snapshot goes to the error
 // message.
 hipError_t wait_with_watchdog(hipStream_t stream, uint32_t timeout_ms, uint32_t* d_cancel, uint32_t* h_one,
-                              const WatchdogView& view) {
+                              const WatchdogView& view, hipStream_t side) {
   using clk = std::chrono::steady_clock;
   const auto limit = clk::now() + std::chrono::milliseconds((timeout_ms ? timeout_ms : 60000) + 3000);
   for (;;) {
@@ -623,9 +623,12 @@ hipError_t wait_with_watchdog(hipStream_t stream, uint32_t timeout_ms, uint32_t*
     if (clk::now() > limit) break;
     std::this_thread::sleep_for(std::chrono::microseconds(50));
   }
-  static hipStream_t side = nullptr;
-  static std::once_flag once;
-  std::call_once(once, [] { (void)hipStreamCreateWithFlags(&side, hipStreamNonBlocking); });
+  if (!side) {
+    static hipStream_t own = nullptr;
+    static std::once_flag once;
+    std::call_once(once, [] { (void)hipStreamCreateWithFlags(&own, hipStreamNonBlocking); });
+    side = own;
+  }
   std::string snap = "watchdog snapshot:";
   if (view.d_ctrl) {
     uint32_t* hb = nullptr;
@@ -857,6 +860,114 @@ extern "C" int mlmq_sssp(const mlmq_graph* g, uint32_t source, uint32_t* dist_ou
   mlmq_config tmp;
   const mlmq_config* c = resolve_config(g, cfg, &tmp);
   return run_single(g, source, dist_out, *c);
+}
+
+namespace {
+
+// Per-device state of the allocation-free solve, set up on its first call on
+// a device: the fixed queue array's address and a stream for the watchdog's
+// cancel store. Calls on one device hold its lock for the whole solve, since
+// they all use the same array.
+struct NoAllocDevice {
+  std::mutex mu;
+  void* scratch = nullptr;
+  hipStream_t side = nullptr;
+  bool ready = false;
+  uint32_t one = 1;
+  uint32_t zero = 0;
+};
+
+int noalloc_device(int dev, NoAllocDevice** out) {
+  static std::mutex mu;
+  static NoAllocDevice devs[64];
+  if (dev < 0 || dev >= 64) return set_error(MLMQ_ERR_DEVICE, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lk(mu);
+  NoAllocDevice& d = devs[dev];
+  if (!d.ready) {
+    hipError_t e = noalloc_scratch(dev, &d.scratch);
+    if (e != hipSuccess) return hip_fail(e, "address of the fixed queue array");
+    e = hipStreamCreateWithFlags(&d.side, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "watchdog stream");
+    d.ready = true;
+  }
+  *out = &d;
+  return MLMQ_OK;
+}
+
+}  // namespace
+
+extern "C" int mlmq_sssp_noalloc(const mlmq_graph* g, uint32_t source, uint32_t* dist_out, const mlmq_config* cfg) {
+  if (!g) return set_error(MLMQ_ERR_INVALID_ARG, "graph is NULL");
+  if (!dist_out) return set_error(MLMQ_ERR_INVALID_ARG, "dist_out is NULL");
+  if (source >= (uint32_t)g->n) return set_error(MLMQ_ERR_INVALID_ARG, "source %u >= n %d", source, g->n);
+  int rc = need_device();
+  if (rc) return rc;
+  mlmq_config tmp;
+  const mlmq_config& c = *resolve_config(g, cfg, &tmp);
+  rc = check_config(&c);
+  if (rc) return rc;
+  if (!is_device_ptr(dist_out)) return set_error(MLMQ_ERR_INVALID_ARG, "dist_out must be device memory");
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "current device");
+  NoAllocDevice* nd = nullptr;
+  rc = noalloc_device(dev, &nd);
+  if (rc) return rc;
+  LaunchShape shape;
+  rc = launch_shape(c, c.l1_type == MLMQ_L1_NONE ? 64u : c.l1_cap, c.l1_type == MLMQ_L1_NEARFAR,
+                    c.l2_type == MLMQ_L2_BUCKET, &shape);
+  if (rc) return rc;
+  // Layout inside the array: queues, descriptor, launch control words, the
+  // overflow flag and one heartbeat word per workgroup.
+  const QueryPlan p = plan_query(g, c, 0, 1);
+  const size_t desc_off = align_up(p.bytes, 256);
+  const size_t batch_off = align_up(desc_off + sizeof(QueryDesc), 256);
+  const size_t flag_off = align_up(batch_off + sizeof(BatchCtrl), 256);
+  const size_t beats_off = align_up(flag_off + 4, 256);
+  const size_t total = align_up(beats_off + 4ull * shape.grid, 256);
+  if (total > kNoAllocScratchBytes)
+    return set_error(MLMQ_ERR_INVALID_ARG,
+                     "queue memory of this solve (%zu bytes) exceeds the %zu bytes of the allocation-free entry point",
+                     total, kNoAllocScratchBytes);
+  hipStream_t stream = reinterpret_cast<hipStream_t>(c.stream);
+  std::lock_guard<std::mutex> lk(nd->mu);
+  char* base = static_cast<char*>(nd->scratch);
+  QueryDesc* d_desc = reinterpret_cast<QueryDesc*>(base + desc_off);
+  BatchCtrl* d_batch = reinterpret_cast<BatchCtrl*>(base + batch_off);
+  uint32_t* d_flag = reinterpret_cast<uint32_t*>(base + flag_off);
+  uint32_t* d_beats = reinterpret_cast<uint32_t*>(base + beats_off);
+  const QueryDesc h_desc = make_desc(g, c, p, base, dist_out, source, shape.grid);
+  const LaunchArgs a = make_args(d_desc, d_batch, 1, shape, c.timeout_ms, d_beats);
+  // The init kernel resets every queue word, counter and control word the
+  // worker reads (the array keeps whatever the previous call left).
+  e = hipMemcpyAsync(d_desc, &h_desc, sizeof(QueryDesc), hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) e = launch_init(d_desc, d_batch, 1, p.init_words, stream);
+  if (e == hipSuccess) e = launch_worker(a, shape.grid, shape.wg, shape.lds, stream);
+  WatchdogView view;  // no snapshot: it would allocate pinned memory
+  nd->one = 1;
+  if (e == hipSuccess) e = wait_with_watchdog(stream, c.timeout_ms, &d_batch->cancel.v, &nd->one, view, nd->side);
+  if (e == hipErrorLaunchTimeOut) return set_error(MLMQ_ERR_TIMEOUT, "device overran its timeout");
+  QueryCtrl h_ctrl;
+  if (e == hipSuccess) e = hipMemcpyAsync(&h_ctrl, h_desc.ctrl, sizeof(QueryCtrl), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return hip_fail(e, "solve");
+  const uint32_t st = h_ctrl.error.v;
+  rc = status_to_code(st);
+  if (rc == MLMQ_OK && h_ctrl.overflow.v && !g->overflow_safe) {
+    // exact overflow test, as in mlmq_sssp
+    uint32_t h_flag = 0;
+    nd->zero = 0;
+    e = hipMemcpyAsync(d_flag, &nd->zero, 4, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = launch_overflow_check(d_desc, d_flag, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(&h_flag, d_flag, 4, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail(e, "overflow check");
+    if (h_flag) rc = set_error(MLMQ_ERR_DISTANCE_OVERFLOW, "a reachable distance does not fit below 2^32-1");
+  } else if (rc != MLMQ_OK) {
+    set_error(rc, "solve failed with device status %u (no capacity retry without allocation)", st);
+  }
+  fill_stats(c.stats_out, h_ctrl, 0.0, 0.0, shape.grid, 0);
+  return rc;
 }
 
 extern "C" int mlmq_bfs(const mlmq_graph* g, uint32_t source, uint32_t* levels_out, const mlmq_config* cfg) {

@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "../../include/mlmq.h"
 #include "mlmq_internal.h"
@@ -52,7 +53,7 @@ struct Slab {
   void* host = nullptr;
   size_t host_bytes = 0;
   hipGraphExec_t graph_exec = nullptr;  // cached captured launch (batch)
-  uint64_t graph_key = 0;
+  std::vector<uint64_t> graph_key;      // every argument baked into graph_exec
 };
 
 struct LaunchShape {
@@ -93,7 +94,9 @@ struct WatchdogView {
   const uint32_t* d_beats = nullptr;  // per-wave heartbeats
   uint32_t nbeats = 0;
 };
+// side: the stream that carries the snapshot reads and the cancel store
+// (nullptr = a library stream created on first use).
 hipError_t wait_with_watchdog(hipStream_t stream, uint32_t timeout_ms, uint32_t* d_cancel, uint32_t* h_one,
-                              const WatchdogView& view);
+                              const WatchdogView& view, hipStream_t side = nullptr);
 
 }  // namespace mlmq

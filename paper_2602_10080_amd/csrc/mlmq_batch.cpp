@@ -23,11 +23,6 @@ constexpr uint32_t kBatchShare = 128;
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
-uint64_t mix(uint64_t h, uint64_t x) {
-  h ^= x + 0x9E3779B97F4A7C15ull + (h << 6) + (h >> 2);
-  return h;
-}
-
 hipStream_t internal_stream() {
   static hipStream_t s = nullptr;
   static std::once_flag once;
@@ -122,11 +117,16 @@ extern "C" int mlmq_sssp_batch(const mlmq_graph* const* graphs, const uint32_t* 
   }
   uint32_t* d_beats = reinterpret_cast<uint32_t*>(base + beats_off);
   const LaunchArgs a = make_args(d_desc, d_batch, nq, shape, lc.timeout_ms, d_beats);
-  uint64_t key = 0x6d6c6d71ull;
-  for (uint64_t x : {(uint64_t)nq, (uint64_t)shape.grid, (uint64_t)shape.wg, (uint64_t)shape.lds,
-                     (uint64_t)init_words, (uint64_t)(uintptr_t)stream, a.timeout_ticks, (uint64_t)shape.l1_cap,
-                     (uint64_t)shape.two})
-    key = mix(key, x);
+  // The captured launch bakes in every kernel argument: the launch shape and
+  // the addresses of the descriptors, control words, results and heartbeats
+  // (which move with the summed plan sizes of the queries before them). The
+  // descriptors' contents are read at run time, so only these must match, and
+  // they are compared in full (no hash).
+  const std::vector<uint64_t> key = {(uint64_t)nq, (uint64_t)shape.grid, (uint64_t)shape.wg, (uint64_t)shape.lds,
+                                     (uint64_t)init_words, (uint64_t)(uintptr_t)stream, a.timeout_ticks,
+                                     a.cap_wait_ticks, (uint64_t)a.l1_cap, (uint64_t)a.l1_two, (uint64_t)a.stage,
+                                     (uint64_t)a.waves, (uint64_t)(uintptr_t)d_desc, (uint64_t)(uintptr_t)d_batch,
+                                     (uint64_t)(uintptr_t)d_res, (uint64_t)(uintptr_t)d_beats};
   hipError_t e = hipMemcpyAsync(d_desc, h_desc, sizeof(QueryDesc) * nq, hipMemcpyHostToDevice, stream);
   if (e == hipSuccess && (!slab->graph_exec || slab->graph_key != key)) {
     if (slab->graph_exec) {
@@ -144,7 +144,7 @@ extern "C" int mlmq_sssp_batch(const mlmq_graph* const* graphs, const uint32_t* 
       if (e == hipSuccess) e = e1;
     }
     if (e == hipSuccess) e = hipGraphInstantiate(&slab->graph_exec, graph, nullptr, nullptr, 0);
-    if (graph) hipGraphDestroy(graph);
+    if (graph) (void)hipGraphDestroy(graph);
     if (e == hipSuccess) slab->graph_key = key;
   }
   if (e == hipSuccess) e = hipGraphLaunch(slab->graph_exec, stream);

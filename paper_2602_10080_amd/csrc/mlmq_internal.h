@@ -187,4 +187,10 @@ hipError_t launch_check(const int32_t* off, const uint64_t* adj, const uint32_t*
                         hipStream_t s);
 hipError_t server_occupancy(size_t lds, int* wgs_per_cu);
 
+// Bytes of the fixed device array behind the allocation-free solve.
+constexpr size_t kNoAllocScratchBytes = 128ull << 20;
+// Device address of that array on `device`, which must be the current device;
+// looked up once per device and cached.
+hipError_t noalloc_scratch(int device, void** out);
+
 }  // namespace mlmq

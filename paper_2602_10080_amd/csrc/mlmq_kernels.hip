@@ -30,6 +30,8 @@
 
 #include "mlmq_internal.h"
 
+#include <mutex>
+
 #include "../../include/mlmq.h"
 
 namespace mlmq {
@@ -161,6 +163,12 @@ __device__ __forceinline__ void beat(uint32_t* b, uint32_t point, uint32_t it) {
   if (b && lane() == 0)
     __hip_atomic_store(b, (point << 24) | (it & 0xFFFFFFu), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
+// Program points inside the worker loop report on one iteration in 64 only:
+// a wave that is stuck still reports within 64 turns of its loop, and the
+// store stays off the per-iteration path.
+__device__ __forceinline__ void beat_loop(uint32_t* b, uint32_t point, uint32_t it) {
+  if ((it & 63u) == 0) beat(b, point, it);
+}
 
 __device__ __forceinline__ bool past_deadline(const Ctx& c) { return (uint64_t)wall_clock64() > c.deadline; }
 __device__ __forceinline__ bool canceled(const Ctx& c) { return uni(ld32(c.cancel)) != 0; }
@@ -257,7 +265,11 @@ __device__ __forceinline__ bool l2_put_block(Ctx& c, uint32_t ring, uint64_t e, 
       beat(c.beat, kPtL2Wait, spins);
       const uint64_t now = (uint64_t)wall_clock64();
       if (spins == 0) t_wait = now;
-      if (now - t_wait > c.cap_wait || now > c.deadline) {
+      if (now > c.deadline) {
+        fail(c, kStTimeout);
+        return false;
+      }
+      if (now - t_wait > c.cap_wait) {
         fail(c, kStCapacity);
         return false;
       }
@@ -965,7 +977,7 @@ __device__ __forceinline__ void run_query(Ctx& c) {
   if (lane() == 0) add32(&c.q.ctrl->active.v, 1u);
   while (!c.stop) {
     ++c.it;
-    beat(c.beat, kPtLoop, c.it);
+    beat_loop(c.beat, kPtLoop, c.it);
     if ((c.it & 63u) == 0 && must_stop(c)) break;
     uint64_t e = 0;
     bool ok = false, got = false;
@@ -980,7 +992,7 @@ __device__ __forceinline__ void run_query(Ctx& c) {
     } else {
       if (c.stage) stage_flush_all(c);
       uint32_t hv, hd, heb, hee;
-      beat(c.beat, kPtHub, c.it);
+      beat_loop(c.beat, kPtHub, c.it);
       if (hub_claim(c, hv, hd, heb, hee)) {
         set_hungry(c, false);
         c.done_acc += 1u;
@@ -990,7 +1002,7 @@ __device__ __forceinline__ void run_query(Ctx& c) {
         if (hd <= uni(ld_label(c.q.dist + hv))) process_range(c, hv, hd, heb, hee);
         continue;
       }
-      beat(c.beat, kPtL2Read, c.it);
+      beat_loop(c.beat, kPtL2Read, c.it);
       got = l2_read(c, e, ok);
       if (got) {
         set_hungry(c, false);
@@ -998,7 +1010,7 @@ __device__ __forceinline__ void run_query(Ctx& c) {
         refill_threshold(c, uni(wave_min(ok ? elem_d(e) : kInf)));
       } else {
         // Idle: the wave holds nothing, so its delayed count can go out.
-        beat(c.beat, kPtIdle, c.it);
+        beat_loop(c.beat, kPtIdle, c.it);
         const uint64_t t0 = (uint64_t)wall_clock64();
         if (c.done_acc) {
           uint32_t r = 0;
@@ -1016,7 +1028,7 @@ __device__ __forceinline__ void run_query(Ctx& c) {
       }
     }
     c.idle = 0;
-    beat(c.beat, kPtProcess, c.it);
+    beat_loop(c.beat, kPtProcess, c.it);
     process_vec(c, e, ok);
   }
   set_hungry(c, false);
@@ -1406,8 +1418,10 @@ hipError_t launch_worker(const LaunchArgs& a, uint32_t grid, uint32_t wg_size, s
   return hipGetLastError();
 }
 
+// The admission-side kernels below run in one-wave workgroups, so that they
+// fit into any free wave slot beside a resident server kernel.
 hipError_t launch_overflow_check(const QueryDesc* d_query, uint32_t* d_flag, hipStream_t s) {
-  hipLaunchKernelGGL(mlmq_overflow_check, dim3(1024), dim3(256), 0, s, d_query, d_flag);
+  hipLaunchKernelGGL(mlmq_overflow_check, dim3(4096), dim3(64), 0, s, d_query, d_flag);
   return hipGetLastError();
 }
 
@@ -1423,9 +1437,9 @@ hipError_t launch_server_worker(const ServerArgs& a, uint32_t grid, size_t lds, 
 
 hipError_t launch_server_admit(const QueryDesc& q, QueryDesc* d_slot, uint64_t* d_join, uint64_t word,
                                uint32_t max_words, hipStream_t s) {
-  uint32_t blocks = (max_words + 255u) / 256u;
-  blocks = blocks < 1u ? 1u : (blocks > 2048u ? 2048u : blocks);
-  hipLaunchKernelGGL(mlmq_server_init, dim3(blocks), dim3(256), 0, s, q, d_slot);
+  uint32_t blocks = (max_words + 63u) / 64u;
+  blocks = blocks < 1u ? 1u : (blocks > 8192u ? 8192u : blocks);
+  hipLaunchKernelGGL(mlmq_server_init, dim3(blocks), dim3(64), 0, s, q, d_slot);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(mlmq_server_publish, dim3(1), dim3(64), 0, s, d_join, word);
@@ -1461,6 +1475,35 @@ hipError_t server_occupancy(size_t lds, int* wgs_per_cu) {
 
 hipError_t worker_occupancy(uint32_t wg_size, size_t lds, int* wgs_per_cu) {
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(wgs_per_cu, mlmq_worker, (int)wg_size, lds);
+}
+
+// ------------------------------------------------------------ allocation-free solve
+
+// Queue memory of the allocation-free single-source solve: one fixed array on
+// every device the library runs on, reserved with the code object and held
+// until the process ends. On the host the name `scratch` is only a stand-in
+// for the device symbol; host code uses the device address below instead,
+// taken once per device with that device current.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t noalloc_scratch(int device, void** out) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_scratch_ptr[device] = ptr;
+  }
+  *out = g_scratch_ptr[device];
+  return hipSuccess;
 }
 
 }  // namespace mlmq

@@ -408,7 +408,12 @@ int mlmq_server_create(const mlmq_graph* const* graphs, int32_t ngraphs, uint64_
   hipError_t e = server_occupancy(s->lds, &per_cu);
   if (e != hipSuccess) return fail(hip_fail(e, "occupancy query"));
   if (per_cu < 1) return fail(set_error(MLMQ_ERR_INVALID_ARG, "server kernel does not fit on a CU"));
-  s->grid = (uint32_t)per_cu * (uint32_t)di->cus;
+  // One workgroup per CU fewer than fit: the admission kernels (query init,
+  // slot opening, overflow check) run beside the resident kernel, and when
+  // registers rather than LDS bound its residency (power-law graphs with a
+  // small L1: 3 waves per SIMD use 504 of 512 VGPRs) a full-size resident
+  // grid would leave them no room until resident waves leave.
+  s->grid = (uint32_t)std::max(1, per_cu - 1) * (uint32_t)di->cus;
   if (cfg && cfg->grid_wgs) s->grid = std::min(s->grid, cfg->grid_wgs);
   for (int32_t i = 0; i < ngraphs; ++i) {
     // at most the graph's own launch size (its config's grid_wgs, else all)

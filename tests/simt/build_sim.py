@@ -62,4 +62,4 @@ def build(out_dir: str, sanitize: bool = False, checked: bool = True) -> str:
 
 
 if __name__ == "__main__":
-    print(build(os.path.join(ROOT, "_work", "sim")))
+    print(build(os.path.join(ROOT, "_build", "simt")))

@@ -25,24 +25,59 @@ def _say(*a):
     sys.stdout.flush()
 
 
-def _solve_and_check(name, csr, src):
+_CACHE = {}
+
+
+def _workload(name):
+    """(csr, source, oracle distances) of a benchmark graph, built once."""
+    if name not in _CACHE:
+        if name == "rmat23":
+            csr = gg.rmat(23, 16, seed=1)
+            src = gg.max_degree_vertex(csr)
+        elif name == "grid2048":
+            csr, src = gg.grid(2048, 2048, 0.05, seed=1), 1024 * 2048 + 1024
+        else:
+            raise KeyError(name)
+        _CACHE[name] = (csr, src, oracle.dijkstra(csr, src))
+    return _CACHE[name]
+
+
+_DEV = {}
+
+
+def _device_graph(name, csr):
+    """The device copy of a cached benchmark graph (uploaded once)."""
+    if name not in _DEV:
+        _DEV[name] = _mlmq().Graph.from_csr(csr)
+    return _DEV[name]
+
+
+def _solve_and_check(name, csr, src, want=None, overrides=None, g=None):
     mlmq = _mlmq()
-    g = mlmq.Graph.from_csr(csr)
+    own = g is None
+    if own:
+        g = mlmq.Graph.from_csr(csr)
     out = mlmq.new_dist(csr.n)
-    _say(f"[full] {name}: n={csr.n} m={csr.m} src={src} config={g.config().as_dict()}")
+    cfg = g.config().copy(**(overrides or {}))
+    _say(f"[full] {name}: n={csr.n} m={csr.m} src={src} config={cfg.as_dict()}")
     for _ in range(2):  # the second run reuses the buffer, as the timed steps do
-        mlmq.sssp(g, src, out=out)
+        _, st = mlmq.sssp(g, src, out=out, config=cfg, stats=True)
     torch.cuda.synchronize()
+    _say(f"[full] {name}: {st['worker_ms']:.2f} ms, retries {st['retries']}, l2 blocks {st['l2_writes']}, "
+         f"work ratio {st['expansions'] / max(1, csr.n):.2f} (per vertex)")
     got = mlmq.to_numpy(out)
     code, where, _ = oracle.certificate(csr, src, got)
     assert code == 0, f"certificate rejects the vector (code {code} at {where})"
-    want = oracle.dijkstra(csr, src)
+    if want is None:
+        want = oracle.dijkstra(csr, src)
     bad = np.nonzero(got != want)[0]
     assert bad.size == 0, f"{bad.size} mismatches, first {bad[:5]}"
     nbad, ms = mlmq.check(g, src, out)
     _say(f"[full] {name}: device check {nbad} violations, edge pass {ms:.3f} ms")
     assert nbad == 0
-    g.close()
+    if own:
+        g.close()
+    return st
 
 
 def test_grid256_source0():
@@ -50,12 +85,33 @@ def test_grid256_source0():
 
 
 def test_road_grid2048_centre():
-    _solve_and_check("grid2048", gg.grid(2048, 2048, 0.05, seed=1), 1024 * 2048 + 1024)
+    csr, src, want = _workload("grid2048")
+    _solve_and_check("grid2048", csr, src, want, g=_device_graph("grid2048", csr))
 
 
 def test_rmat23_highest_degree_source():
-    csr = gg.rmat(23, 16, seed=1)
-    _solve_and_check("rmat23", csr, gg.max_degree_vertex(csr))
+    csr, src, want = _workload("rmat23")
+    _solve_and_check("rmat23", csr, src, want, g=_device_graph("rmat23", csr))
+
+
+# The bucket L2 (Section 4.2) at full size under each L1 policy over it, and
+# SLF over buckets (the paper's best power-law combination in Section 5):
+# bucket width 2^6 around the graphs' mean weight of 128, 32 buckets.
+BUCKET_CONFIGS = {
+    "NF-DQ-d6": dict(l1_type=2, l2_type=1, delta2_log2=6, bmax=32, bnum=4),
+    "V-DQ-d6": dict(l1_type=1, l2_type=1, delta2_log2=6, bmax=32, bnum=4, l1_flush_wb=64),
+    "FQ-DQ-d6": dict(l1_type=3, l2_type=1, delta2_log2=6, bmax=32, bnum=4, delta1=64),
+    "SLF-DQ-d6": dict(l1_type=4, l2_type=1, delta2_log2=6, bmax=32, bnum=4),
+}
+
+
+@pytest.mark.parametrize("cfg_name", list(BUCKET_CONFIGS))
+@pytest.mark.parametrize("name", ["rmat23", "grid2048"])
+def test_bucket_l2_full_size(name, cfg_name):
+    csr, src, want = _workload(name)
+    st = _solve_and_check(f"{name}/{cfg_name}", csr, src, want, dict(BUCKET_CONFIGS[cfg_name], timeout_ms=20000),
+                          g=_device_graph(name, csr))
+    assert st["status"] == 0
 
 
 def test_uniform_4m_wide_weights_sampled_sources():
@@ -110,24 +166,21 @@ def test_serving_mix_on_serving_graphs():
 def test_bfs_rmat23_and_road_grid2048():
     """Breadth-first levels at the benchmark's sizes equal the oracle's BFS."""
     mlmq = _mlmq()
-    for name, csr, src in [("grid2048", gg.grid(2048, 2048, 0.05, seed=1), 1024 * 2048 + 1024),
-                           ("rmat23", (c := gg.rmat(23, 16, seed=1)), gg.max_degree_vertex(c))]:
-        g = mlmq.Graph.from_csr(csr)
+    for name in ("grid2048", "rmat23"):
+        csr, src, _ = _workload(name)
+        g = _device_graph(name, csr)
         _say(f"[full] bfs {name}")
         out = mlmq.bfs(g, src)
         torch.cuda.synchronize()
         assert np.array_equal(mlmq.to_numpy(out), oracle.bfs(csr, src)), name
-        g.close()
 
 
 def test_check_perturbed_road_grid2048():
     """The device check at full size counts the failed conditions of a
     perturbed vector exactly."""
     mlmq = _mlmq()
-    csr = gg.grid(2048, 2048, 0.05, seed=1)
-    src = 1024 * 2048 + 1024
-    g = mlmq.Graph.from_csr(csr)
-    want = oracle.dijkstra(csr, src)
+    csr, src, want = _workload("grid2048")
+    g = _device_graph("grid2048", csr)
     d = want.copy()
     rng = np.random.default_rng(3)
     for v in rng.choice(np.nonzero(want != oracle.UNREACHABLE)[0], 5, replace=False):
@@ -136,4 +189,3 @@ def test_check_perturbed_road_grid2048():
     t = torch.from_numpy(d.view(np.int32)).cuda()
     nbad, _ = mlmq.check(g, src, t)
     assert nbad == check_count(csr, src, d) and nbad > 0
-    g.close()
