@@ -77,7 +77,7 @@ def reach(csr, dist):
     return int(fin.sum()), int(csr.degrees()[fin].sum())
 
 
-def measure(mlmq, torch, csr, src, overrides, steps, warmup):
+def measure(mlmq, torch, csr, src, overrides, steps, warmup, bare=False):
     g = mlmq.Graph.from_csr(csr)
     cfg = g.config()
     for k, v in (json.loads(overrides) if overrides else {}).items():
@@ -98,6 +98,11 @@ def measure(mlmq, torch, csr, src, overrides, steps, warmup):
         wms.append(st["worker_ms"])
         last = st
     total = time.perf_counter() - t_all
+    if bare:
+        dist = mlmq.to_numpy(out)
+        g.close()
+        return dict(walls=walls, kernel_ms=kms, worker_ms=wms, stats=last, dist=dist, total=total, cfg=cfg,
+                    host_output_ms=None, check_violations=None, single_pass_ms=None)
     # the same solve into a host buffer: the library copies the distances back
     # (PCIe-inclusive time; never the headline value)
     host_out = np.empty(csr.n, np.uint32)
@@ -206,6 +211,53 @@ def cpu_baseline(csr, src, gpu_dist, max_seconds=30.0):
                 seconds=t, sp_depth=int(depth) if code == 0 else None), bool(np.array_equal(want, gpu_dist))
 
 
+def host_info():
+    """Host CPU of this box: logical CPUs the OS reports, the model name, and
+    the worker threads a CPU baseline uses (the host share of one GPU: at most
+    16 threads)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    nproc = os.cpu_count() or 1
+    return dict(nproc=nproc, cpu_model=model, threads=min(16, nproc))
+
+
+def oracle_pool(csrs, srcs, gpu_out, what, max_seconds=None):
+    """The oracle over a thread pool (one query per thread; the C oracle
+    releases the GIL), timed as a throughput baseline. Every finished query is
+    compared with the GPU's vector (gpu_out(i), a host array). With max_seconds, queries are submitted in
+    order until the time bound is reached (a bounded sample)."""
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+    hi = host_info()
+    done, equal = 0, True
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=hi["threads"]) as ex:
+        futs = []
+        for i in range(len(srcs)):
+            if max_seconds is not None and time.perf_counter() - t0 > max_seconds:
+                break
+            futs.append((i, ex.submit(oracle.dijkstra, csrs[i], srcs[i])))
+            if max_seconds is not None and len(futs) >= hi["threads"]:
+                # keep at most one round of queries in flight so the bound holds
+                j, f = futs.pop(0)
+                equal = equal and bool(np.array_equal(f.result(), gpu_out(j)))
+                done += 1
+        for j, f in futs:
+            equal = equal and bool(np.array_equal(f.result(), gpu_out(j)))
+            done += 1
+    t = time.perf_counter() - t0
+    cpu = dict(value=done / t, unit="queries/s", cores=hi["threads"], kind="oracle",
+               sample=f"{done} of {what}, one query per thread, {t:.1f} s", host=hi)
+    return cpu, equal
+
+
 def bench_batch(mlmq, torch, tune_ms, nrmat=256, ngrid=64):
     """Many queries in one persistent launch vs the same queries as sequential
     plain solves (graphs resident, autotuned config per graph for both)."""
@@ -239,26 +291,15 @@ def bench_batch(mlmq, torch, tune_ms, nrmat=256, ngrid=64):
     torch.cuda.synchronize()
     t_seq = time.perf_counter() - t0
     same = all(torch.equal(a, b) for a, b in zip(outs, seq))
-    import oracle
-    pick = [0, nrmat - 1, nrmat, nrmat + ngrid - 1]
-    exact = all(np.array_equal(mlmq.to_numpy(outs[i]), oracle.dijkstra(csrs[i], srcs[i])) for i in pick)
-    nq = nrmat + ngrid
-    # CPU baseline: the oracle, one query per thread over all host cores, on a
-    # sample of the batch in the same RMAT/grid proportion
-    from concurrent.futures import ThreadPoolExecutor
-    cores = min(16, os.cpu_count() or 1)  # the host share of one GPU
-    sample = list(range(0, nrmat, max(1, nrmat // 16)))[:16] + list(range(nrmat, nq, max(1, ngrid // 4)))[:4]
-    t0 = time.perf_counter()
-    with ThreadPoolExecutor(max_workers=cores) as ex:
-        list(ex.map(lambda i: oracle.dijkstra(csrs[i], srcs[i]), sample))
-    t_cpu = time.perf_counter() - t0
-    cpu = dict(value=len(sample) / t_cpu, unit="queries/s", cores=cores, kind="oracle",
-               sample=f"{len(sample)} of the batch's queries ({sum(1 for i in sample if i < nrmat)} RMAT-20, "
-                      f"{sum(1 for i in sample if i >= nrmat)} grid1024), one per thread")
+    # CPU baseline: the oracle, one query per thread over the host's CPU share
+    # for one GPU, on every query of the batch; its vectors also check every
+    # batched output element by element
+    cpu, exact = oracle_pool(csrs, srcs, lambda i: mlmq.to_numpy(outs[i]),
+                             f"all {nq} queries of the batch ({nrmat} RMAT-20, {ngrid} grid1024)")
     res = dict(queries=nq, cpu_baseline=cpu, workload=f"{nrmat} sources RMAT-20 + {ngrid} sources grid1024 p0.05",
                batch_s=t_batch, sequential_s=t_seq, batch_qps=nq / t_batch, sequential_qps=nq / t_seq,
                speedup=t_seq / t_batch, statuses_ok=all(x == 0 for x in status),
-               batch_equals_sequential=same, oracle_checked=len(pick), oracle_equal=exact,
+               batch_equals_sequential=same, oracle_checked=nq, oracle_equal=exact,
                tuned={"rmat20": cr.as_dict(), "grid1024": cd.as_dict()})
     log(f"[bench] batch: {nq} queries {t_batch:.3f}s ({nq / t_batch:.1f} q/s) vs sequential {t_seq:.3f}s "
         f"({nq / t_seq:.1f} q/s), same={same} oracle={exact}")
@@ -335,13 +376,18 @@ def bench_serve(mlmq, torch, nreq, load, budget_gb, seed=7):
     srv_lat = [(b - t0_ns) / 1e9 - arrive[i] for i, (a, b) in enumerate(times)]
     srv_span = (max(b for _, b in times) - t0_ns) / 1e9 - arrive[0]
     same = all(np.array_equal(mlmq.to_numpy(outs[i]), keep[i]) for i in keep)
+    # CPU baseline: the oracle on the trace's requests in arrival order, one per
+    # thread, for about 20 s; each vector is compared with the served one
+    cpu, cpu_equal = oracle_pool([csrs[g] for g in gid], [int(x) for x in src], lambda i: mlmq.to_numpy(outs[i]),
+                                 f"the {nreq} requests in arrival order", max_seconds=20.0)
     f50, f99 = _percentiles(fifo_lat)
     s50, s99 = _percentiles(srv_lat)
     res = dict(requests=nreq, graphs=names, arrival_rate_qps=lam, fifo_service_rate_qps=mu, load=load,
                mem_budget_gb=budget_gb,
                server_qps=nreq / srv_span, server_p50_ms=s50 * 1e3, server_p99_ms=s99 * 1e3,
                fifo_qps=nreq / fifo_span, fifo_p50_ms=f50 * 1e3, fifo_p99_ms=f99 * 1e3,
-               statuses_ok=all(x == 0 for x in status), served_equals_alone=same, compared=len(keep))
+               statuses_ok=all(x == 0 for x in status), served_equals_alone=same, compared=len(keep),
+               cpu_baseline=cpu, oracle_equal=cpu_equal)
     log(f"[bench] serve: server {res['server_qps']:.1f} q/s p50 {res['server_p50_ms']:.2f} ms "
         f"p99 {res['server_p99_ms']:.2f} ms | FIFO {res['fifo_qps']:.1f} q/s p50 {res['fifo_p50_ms']:.2f} ms "
         f"p99 {res['fifo_p99_ms']:.2f} ms | same={same}")
@@ -350,24 +396,156 @@ def bench_serve(mlmq, torch, nreq, load, budget_gb, seed=7):
     return res
 
 
+def pq_study(mlmq, torch, reps=3):
+    """Section 5's priority-queue case study on synthetic stand-ins: the L2
+    priority queue (L2PQ) and the multi-queue (L2MPQ, 16 queues) alone and
+    under L0 + L1 queues, at several launch sizes, beside the FIFO and bucket
+    L2 under the same L0 + L1. Median device time of the persistent kernel
+    and work ratio (expansions / reachable vertices) per point; every output
+    is checked by the device optimality check."""
+    graphs = {"road512": (gg.grid(512, 512, 0.05, seed=11), 256 * 512 + 256),
+              "rmat20": (lambda c: (c, gg.max_degree_vertex(c)))(gg.rmat(20, 16, seed=13))}
+    fams = {
+        "L2PQ": dict(l0_rows=0, l1_type=0, l2_type=2, pnum=1),
+        "L2MPQ16": dict(l0_rows=0, l1_type=0, l2_type=2, pnum=16),
+        "L0L1-L2PQ": dict(l0_rows=1, l1_type=2, l2_type=2, pnum=1),
+        "L0L1-L2MPQ16": dict(l0_rows=1, l1_type=2, l2_type=2, pnum=16),
+        "L0L1-L2V": dict(l0_rows=1, l1_type=2, l2_type=0),
+        "L0L1-L2DQ": dict(l0_rows=1, l1_type=2, l2_type=1),
+    }
+    out = {}
+    for gname, (csr, src) in graphs.items():
+        g = mlmq.Graph.from_csr(csr)
+        base = g.config()
+        d = mlmq.new_dist(csr.n)
+        rows = []
+        for fam, kw in fams.items():
+            for waves in (128, 512, 2048):
+                cfg = base.copy(**kw, grid_wgs=waves, timeout_ms=20000, th_hub=0)
+                ms, st = [], None
+                try:
+                    for _ in range(reps):
+                        _, st = mlmq.sssp(g, src, out=d, config=cfg, stats=True)
+                        ms.append(st["worker_ms"])
+                    bad, _ = mlmq.check(g, src, d)
+                except mlmq.MlmqError as e:
+                    rows.append(dict(queues=fam, waves=waves, error=str(e)[:120]))
+                    log(f"[bench] pq study {gname} {fam} {waves}: {e}")
+                    continue
+                n_reach = int((mlmq.to_numpy(d) != INF).sum())
+                rows.append(dict(queues=fam, waves=waves, worker_ms=statistics.median(ms),
+                                 work_ratio=st["expansions"] / max(1, n_reach), l2_writes=st["l2_writes"],
+                                 violations=int(bad)))
+                log(f"[bench] pq study {gname} {fam} waves {waves}: {statistics.median(ms):.2f} ms, "
+                    f"work {rows[-1]['work_ratio']:.2f}, violations {bad}")
+        g.close()
+        out[gname] = rows
+    return out
+
+
+# ------------------------------------------------------------ counter summaries
+
+COUNTER_PASSES = {
+    # pass name: counters (each pass fits the per-block limits of one rocprofv3 run)
+    "fetch": ["FETCH_SIZE"],
+    "write": ["WRITE_SIZE", "TCC_EA0_WRREQ_DRAM_sum"],
+    "dram": ["TCC_EA0_RDREQ_DRAM_32B_sum", "TCC_EA0_RDREQ_DRAM_sum", "TCC_EA0_WRREQ_ATOMIC_DRAM_32B_sum",
+             "TCC_EA0_ATOMIC_sum"],
+    "cache": ["TCC_HIT_sum", "TCC_MISS_sum", "SQ_INSTS_LDS", "SQ_LDS_BANK_CONFLICT", "SQ_WAVE_CYCLES",
+              "SQ_BUSY_CYCLES", "SQ_WAIT_INST_ANY"],
+}
+
+
+def _counter_rows(path):
+    """{dispatch id: (kernel name, {counter: value})} from a rocprofv3 counter CSV."""
+    import csv
+    out = {}
+    with open(path) as fh:
+        for r in csv.DictReader(fh):
+            d = out.setdefault(int(r["Dispatch_Id"]), [r["Kernel_Name"], {}])
+            d[1][r["Counter_Name"]] = d[1].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    return out
+
+
+def summarize_counters(root, workloads, warmup, steps):
+    """Per-launch counter values of the persistent kernel from the counter
+    passes under root/<pass>/ (run with --bare, so each workload contributes
+    warmup + steps launches in order), the copy calibration from
+    root/copy_<pass>/, and the traffic record per workload."""
+    import glob
+    import hashlib
+    per = {w: {} for w in workloads}
+    calib = {}
+    for pas in COUNTER_PASSES:
+        f = glob.glob(os.path.join(root, pas, "**", "*counter_collection.csv"), recursive=True)
+        if f:
+            rows = _counter_rows(f[0])
+            launches = [v for _, v in sorted(rows.items()) if "mlmq_worker" in v[0]]
+            k = warmup + steps
+            if len(launches) != k * len(workloads):
+                raise SystemExit(f"{pas}: {len(launches)} worker launches, expected {k * len(workloads)}")
+            for i, w in enumerate(workloads):
+                timed = launches[i * k + warmup:(i + 1) * k]
+                for c in timed[0][1]:
+                    per[w][c] = statistics.mean(t[1][c] for t in timed)
+        f = glob.glob(os.path.join(root, "copy_" + pas, "**", "*counter_collection.csv"), recursive=True)
+        if f:
+            rows = _counter_rows(f[0])
+            cp = [v for _, v in sorted(rows.items()) if "copyBuffer" in v[0]]
+            big = [v for v in cp if v[1].get(COUNTER_PASSES[pas][0], 0) > 0]
+            for c in big[-1][1]:
+                calib[c] = statistics.mean(v[1][c] for v in big[-3:])
+    sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    copy_kib = 1 << 20  # the copy probe moves 1 GiB each way
+    out = {}
+    for w, c in per.items():
+        if "FETCH_SIZE" not in c or "WRITE_SIZE" not in c:
+            continue
+        fs = copy_kib / calib["FETCH_SIZE"] if "FETCH_SIZE" in calib else 1.0
+        ws = copy_kib / calib["WRITE_SIZE"] if "WRITE_SIZE" in calib else 1.0
+        rec = dict(kernel="mlmq::mlmq_worker", workload=w, kernel_sha256=sha, launches_averaged=steps,
+                   raw_fetch_kib_per_launch=c["FETCH_SIZE"], raw_write_kib_per_launch=c["WRITE_SIZE"],
+                   fetch_scale=fs, write_scale=ws,
+                   fetch_bytes_per_launch=c["FETCH_SIZE"] * 1024 * fs,
+                   write_bytes_per_launch=c["WRITE_SIZE"] * 1024 * ws,
+                   counters_per_launch=c, copy_calibration=calib)
+        if "TCC_EA0_RDREQ_DRAM_32B_sum" in c:
+            rec["dram_read_bytes_per_launch"] = c["TCC_EA0_RDREQ_DRAM_32B_sum"] * 32
+        out[w] = rec
+        with open(os.path.join(ROOT, "profiles", f"traffic_mlmq_worker_{w}.json"), "w") as fh:
+            json.dump(rec, fh, indent=1)
+    print(json.dumps({w: {k: v for k, v in r.items() if k not in ("counters_per_launch", "copy_calibration")}
+                      for w, r in out.items()}, indent=1))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="rmat23")
-    ap.add_argument("--also", default="grid2048", help="comma-separated extra workloads ('' for none)")
+    ap.add_argument("--also", default="grid2048,grid256", help="comma-separated extra workloads ('' for none)")
     ap.add_argument("--config", default="", help="JSON overrides of the queue config (primary workload)")
     ap.add_argument("--also-config", default="", help="JSON overrides for the extra workloads")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch", type=int, default=1, help="run the batched-form comparison (0/1)")
     ap.add_argument("--tune-ms", type=int, default=3000, help="autotuner budget per graph (batch)")
-    ap.add_argument("--serve", type=int, default=1000, help="serving requests (0 = skip)")
+    ap.add_argument("--serve", type=int, default=2000, help="serving requests (0 = skip)")
     ap.add_argument("--serve-load", type=float, default=1.5, help="arrival rate / FIFO service rate")
     ap.add_argument("--serve-budget-gb", type=float, default=8.0)
+    ap.add_argument("--bare", action="store_true",
+                    help="only the warm-up and timed solves of each workload (for counter passes)")
+    ap.add_argument("--summarize-counters", default="",
+                    help="directory of rocprofv3 counter passes: write profiles/traffic_mlmq_worker_<w>.json and exit")
+    ap.add_argument("--pq-study", action="store_true",
+                    help="also run the priority-queue case study (road512, rmat20) into the detail section")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB three times (calibrates HBM counters)")
     args = ap.parse_args()
+    if args.summarize_counters:
+        workloads = [args.workload] + [w for w in args.also.split(",") if w]
+        summarize_counters(args.summarize_counters, workloads, args.warmup, args.steps)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               "(the single-source solve runs on one device)", file=sys.stderr)
@@ -397,7 +575,7 @@ def main():
         csr, src, desc = make_workload(name)
         log(f"[bench] {name}: n={csr.n} m={csr.m} generated in {time.perf_counter() - t0:.1f}s")
         res = measure(mlmq, torch, csr, src, args.config if i == 0 else args.also_config, args.steps,
-                      args.warmup)
+                      args.warmup, bare=args.bare)
         s = summarize(name, desc, csr, src, res, res["cfg"])
         log(f"[bench] {name}: {s['ms_per_step']:.3f} ms/step wall, kernel {s['kernel_ms']:.3f} ms, "
             f"{s['gteps']:.2f} GTEPS, work ratio {s['work_ratio']:.2f}")
@@ -405,36 +583,59 @@ def main():
             log(f"[bench] {name}: device check {s['device_check_violations']} violations; one sweep of all edges "
                 f"{s['single_pass_ms']:.3f} ms ({s['single_pass_gedges']:.1f} G edges/s), solve scans "
                 f"{s['scan_gedges']:.1f} G edges/s = {s['scan_vs_single_pass']:.2f} of that")
+        if args.bare:
+            results[name] = s
+            if i == 0:
+                primary = s
+            continue
         if not args.no_cpu_baseline:
             cb, ok = cpu_baseline(csr, src, res["dist"])
             s["cpu_baseline"] = cb
             s["verified_against_oracle"] = ok
             log(f"[bench] {name}: oracle {cb['seconds']:.2f} s ({cb['value']:.4f} GTEPS), match={ok}")
-        if name in ("rmat23", "grid2048"):
+        if name in ("rmat23", "grid2048", "grid256"):
             s["bfs"] = bench_bfs(mlmq, torch, csr, src)
             depth = s.get("cpu_baseline", {}).get("sp_depth")
             if depth is not None and name.startswith("grid"):
-                # latency floor of a high-diameter graph: fewest-hop depth of the
-                # shortest-path DAG x the per-level time of the breadth-first run
-                # on the same queues (on power-law graphs a level is throughput-
-                # bound, not a round trip, and the floor says nothing)
-                floor = (depth + 1) * s["bfs"]["us_per_level"] / 1e3
+                # latency floors of a high-diameter graph (on power-law graphs a
+                # level is throughput-bound, not a round trip, and no floor is
+                # given): the fewest-hop depth of the shortest-path DAG times
+                # (a) the time of one dependent relaxation hop (row bounds, edge
+                # word, atomicMin, each waiting for the previous) measured by a
+                # probe kernel with no queue at all, independent of the solver;
+                # (b) the per-level time of the breadth-first run on the same
+                # queues (the solver's own round trip per level)
+                g = mlmq.Graph.from_csr(csr)
+                hop_ns, hand_ns = mlmq.latency_probe(g, src, 8192)
+                g.close()
+                floor = (depth + 1) * hop_ns / 1e6
+                bfs_floor = (depth + 1) * s["bfs"]["us_per_level"] / 1e3
                 s["sp_depth"] = int(depth)
+                s["hop_probe_ns"] = hop_ns
+                s["handoff_probe_ns"] = hand_ns
                 s["latency_floor_ms"] = floor
                 s["vs_latency_floor"] = s["worker_ms"] / floor
-                log(f"[bench] {name}: shortest-path depth {depth} hops; latency floor {floor:.2f} ms; "
-                    f"solve = {s['vs_latency_floor']:.2f} x floor")
+                s["bfs_level_floor_ms"] = bfs_floor
+                s["vs_bfs_level_floor"] = s["worker_ms"] / bfs_floor
+                log(f"[bench] {name}: shortest-path depth {depth} hops; dependent hop {hop_ns:.0f} ns, "
+                    f"hand-off {hand_ns:.0f} ns; latency floor {floor:.2f} ms (solve = {s['vs_latency_floor']:.2f} x); "
+                    f"breadth-first level floor {bfs_floor:.2f} ms (solve = {s['vs_bfs_level_floor']:.2f} x)")
         results[name] = s
         if i == 0:
             primary = s
         del csr, res
 
+    if args.bare:
+        print(json.dumps({k: {kk: v[kk] for kk in ("workload", "ms_per_step", "worker_ms", "gteps")}
+                          for k, v in results.items()}), flush=True)
+        return
     stream_gbs = stream_probe(torch)
     log(f"[bench] stream probe (1 GiB device copy): {stream_gbs:.0f} GB/s")
     for s in results.values():
         s["achieved_vs_stream"] = s["achieved_gbs"] / stream_gbs
     batch = bench_batch(mlmq, torch, args.tune_ms) if args.batch else None
     serving = bench_serve(mlmq, torch, args.serve, args.serve_load, args.serve_budget_gb) if args.serve else None
+    pq = pq_study(mlmq, torch) if args.pq_study else None
 
     p = primary
     line = {
@@ -462,6 +663,8 @@ def main():
         "serving": serving,
         "detail": {k: {kk: vv for kk, vv in v.items() if kk not in ("config",)} for k, v in results.items()},
     }
+    if pq is not None:
+        line["pq_case_study"] = pq
     print(json.dumps(line), flush=True)
 
 

@@ -20,6 +20,13 @@
  *   - Out-parameters are written only on MLMQ_OK (distance buffers may have
  *     been partly written on failure).
  *   - All pointers are plain host or device addresses; sizes are element counts.
+ *   - Calls may come from several host threads at once, on different streams
+ *     (graphs are immutable after create; the library's queue memory pool and
+ *     caches are locked). Solves return after their work on the stream is
+ *     done: the call's status (capacity retry, the exact overflow test, the
+ *     watchdog) is decided on the host from the device's status word, so
+ *     there is no asynchronous variant of mlmq_sssp; the server
+ *     (submit / poll / wait) is the asynchronous form.
  */
 #ifndef MLMQ_H_
 #define MLMQ_H_
@@ -42,7 +49,13 @@ extern "C" {
 
 #define MLMQ_UNREACHABLE 0xFFFFFFFFu
 
-/* mlmq_graph_create flags */
+/*
+ * mlmq_graph_create flags. There is no flag to borrow the caller's arrays in
+ * place: the library stores each edge as one 8-byte word (column | weight <<
+ * 32), so one coalesced load brings a lane both the neighbour and the weight,
+ * and a caller's separate col[] / w[] arrays cannot serve as that layout.
+ * Device arrays are therefore always copied (and packed) on the device.
+ */
 #define MLMQ_MEM_HOST 0u   /* CSR arrays are host memory; they are copied to the device */
 #define MLMQ_MEM_DEVICE 1u /* CSR arrays are device memory; they are copied on the device */
 
@@ -61,6 +74,9 @@ extern "C" {
 /* L2 (HBM) queue types, Section 4.2 and Table 1 */
 #define MLMQ_L2_FIFO 0   /* L2V: block-based lock-free FIFO ring */
 #define MLMQ_L2_BUCKET 1 /* L2DQ: bmax FIFO rings as buckets of width delta2 */
+#define MLMQ_L2_PQ 2     /* L2PQ (pnum = 1): a heap of sorted 64-element batches with a lock per node;
+                            L2MPQ (pnum > 1): pnum such heaps, each wave reading its own and writing
+                            to all of them in turn */
 
 /* Counters a solve reports (summed over all waves). */
 typedef struct mlmq_stats {
@@ -93,6 +109,8 @@ typedef struct mlmq_stats {
  */
 typedef struct mlmq_config {
   uint32_t struct_size;
+  /* L0 lives in VGPRs, one element per lane per row, so its capacity is set in
+     rows of 64 elements rather than in elements */
   uint8_t l0_rows;   /* L0 capacity in 64-element rows per wave, 0..4 (0 = L0 off) */
   uint8_t l1_type;   /* MLMQ_L1_* */
   uint8_t l2_type;   /* MLMQ_L2_* */
@@ -102,12 +120,15 @@ typedef struct mlmq_config {
   uint32_t l1_cap;      /* L1 capacity per workgroup in elements (power of two, 64..8192) */
   uint32_t l1_flush_wb; /* L1V: flush all of L1 to L2 after every wb L1 writes (0 = never) */
   uint32_t delta1;      /* L1NF / L1FQ threshold step (distance units, >= 1) */
-  uint32_t delta2_log2; /* L2 bucket width = 2^delta2_log2 */
+  uint32_t delta2_log2; /* L2 bucket width = 2^delta2_log2 (a power of two: the bucket of a distance is
+                           a shift on the hot path, not a division) */
   uint32_t bmax;        /* L2 bucket count (1..64) */
   uint32_t bnum;        /* buckets scanned per L2 read (1..bmax) */
   uint32_t th_v;        /* degree above which a whole wave expands one vertex */
   uint32_t th_hub;      /* degree above which edges are split into grid-wide chunks (0 = off) */
   uint32_t hub_chunk;   /* edges per grid-wide chunk (multiple of 64) */
+  /* (the L2 block size is not a knob: a block is 64 elements, one per lane of
+     the wave that writes or reads it) */
   uint32_t wg_size;     /* threads per workgroup: 64 (one wave; L1 is private to it) */
   uint32_t grid_wgs;    /* persistent workgroups (0 = as many as fit on the device) */
   uint64_t l2_capacity; /* L2 elements per query (0 = automatic); grows on overflow */
@@ -115,6 +136,11 @@ typedef struct mlmq_config {
   uint32_t timeout_ms;  /* device-side watchdog per solve (0 = 60000) */
   uint32_t max_retries; /* capacity-overflow retries with a doubled L2 (default 3) */
   mlmq_stats* stats_out; /* nullable: receives counters of the solve */
+  uint32_t donate_min;  /* spill threshold for idle waves: a wave whose L1 main (near) ring holds at
+                           least this many items hands the older half to L2 while other waves of the
+                           query find no work (0 = automatic: 64 on graphs of >= 2^21 vertices, else
+                           32; breadth-first runs 32); else 16..65536 */
+  uint32_t pnum;        /* MLMQ_L2_PQ: number of priority queues, 1..64 (1 = L2PQ, more = L2MPQ) */
 } mlmq_config;
 
 typedef struct mlmq_graph mlmq_graph;   /* opaque; immutable after create */
@@ -226,6 +252,25 @@ int mlmq_check(const mlmq_graph* g, uint32_t source, const uint32_t* dist, void*
                float* edge_pass_ms_out);
 
 /*
+ * Latency probes on g's device copy, a floor for high-diameter graphs that
+ * does not come from the solver itself. (1) One lane follows `hops` hops
+ * from source, each hop doing the memory operations of one relaxation in
+ * dependence: the row bounds of the current vertex, then one of its edge
+ * words, then an agent-scope atomicMin on the neighbour's label (in a scratch
+ * label array) whose returned value the next hop waits for; *hop_ns_out =
+ * average time per hop. (2) Two workgroups (on different XCDs) take turns
+ * incrementing one device word, each waiting to see the other's store;
+ * *handoff_ns_out = one hand-off (half a round trip). stream: hipStream_t
+ * (NULL = null stream); blocks until done. hops in [1, 2^24]. A solve along a
+ * shortest-path tree of depth D cannot finish faster than about D hops.
+ * Scratch (4n bytes) is allocated and freed by the call. MLMQ_ERR_TIMEOUT if
+ * the second workgroup never answered (each wait gives up after 2 s).
+ */
+int mlmq_latency_probe(const mlmq_graph* g, uint32_t source, uint32_t hops, void* stream, double* hop_ns_out,
+                       double* handoff_ns_out);
+
+/*
+ * Many queries in one persistent launch./*
  * Many queries in one persistent launch. Query i solves graphs[i] from
  * sources[i] into dist_outs[i] (device memory, n_i uint32 each). cfgs may be
  * NULL (per-graph autotuned/default) or hold one config per query; launch
@@ -237,10 +282,60 @@ int mlmq_sssp_batch(const mlmq_graph* const* graphs, const uint32_t* sources, ui
                     int32_t nq, const mlmq_config* const* cfgs, int32_t* per_query_status);
 
 /*
- * Empirical autotuner (Section 3.5's input-adaptive configuration, as a timed
- * search): candidates pruned by the Table 2 features, each timed on seeded
- * sources; the best is cached for the graph (used by cfg == NULL) and written
- * to *out. budget_ms bounds the search time (0 = default 2000).
+ * Input-adaptive configuration (Section 3.5). The library holds a fixed list
+ * of candidate configurations ("templates"): each L1 policy over each L2 type,
+ * with and without register queues, with the near-far/filter step, bucket
+ * width, L1 capacity, launch size, donation threshold, L1V flush period and
+ * whole-wave threshold set relative to the graph's Table 2 features or to the
+ * device. A learned selector -- a random-forest regressor trained offline on
+ * timings of every template over a seeded synthetic corpus of grids, RMAT and
+ * uniform graphs -- predicts each template's runtime relative to the best
+ * template on that graph from the Table 2 features and the template's knobs.
+ * The workgroup size is not searched: a workgroup is always one wave64.
+ */
+
+/* Number of templates (ids 0 .. count-1). */
+int32_t mlmq_candidate_count(void);
+
+/*
+ * Template t as a config for graph g (t = -1: the feature-driven default that
+ * cfg == NULL uses before any tuning). out->struct_size must be set; its
+ * stream and stats_out are kept. Needs a device (the launch size depends on
+ * its compute units). MLMQ_ERR_INVALID_ARG for t out of range.
+ */
+int mlmq_candidate_config(const mlmq_graph* g, int32_t t, mlmq_config* out);
+
+/*
+ * Host only (no device needed). x receives the selector's 20 model inputs for
+ * template t on a graph with features f (the Table 2 features, sizes as log2,
+ * spreads relative to their means, then the template's knobs); the training
+ * script builds its data with this call.
+ */
+int mlmq_select_inputs(const mlmq_features* f, int32_t t, float* x);
+
+/*
+ * Host only. Ranks the templates for features f by the selector's predicted
+ * relative performance: order[0 .. min(cap, count)) receives template ids,
+ * best first (ties in list order); scores (nullable, count floats) receives
+ * each template's prediction (1 = as fast as the best template).
+ */
+int mlmq_select_rank(const mlmq_features* f, int32_t* order, float* scores, int32_t cap);
+
+/*
+ * The selector's top template for g as a config, without timing anything and
+ * without caching it (the feature-driven default if no model is built in).
+ * out->struct_size must be set; stream and stats_out are kept.
+ */
+int mlmq_select(const mlmq_graph* g, mlmq_config* out);
+
+/*
+ * Autotuner (Section 3.5's input-adaptive configuration, measured): the
+ * feature-driven default, then the templates in the selector's order, each
+ * timed on three seeded sources (the highest-degree vertex and two drawn
+ * among vertices with edges) until budget_ms is spent (0 = 2000); a candidate
+ * may not run longer than 4x the best total so far. The fastest is cached for
+ * the graph (used by cfg == NULL) and written to *out (nullable; struct_size
+ * must be set; its stream, used for the timing runs, and stats_out are kept).
  */
 int mlmq_autotune(mlmq_graph* g, uint32_t budget_ms, mlmq_config* out);
 
@@ -259,7 +354,8 @@ int mlmq_autotune(mlmq_graph* g, uint32_t budget_ms, mlmq_config* out);
  * The library's streams are non-blocking; hipDeviceSynchronize waits for the
  * resident kernel, so callers use stream or event synchronisation while a
  * server is alive. destroy cancels pending queries, waits for running ones
- * and stops the kernel.
+ * and stops the kernel. cfg (nullable) replaces every graph's config (one
+ * resident kernel serves all graphs; NULL = each graph's own config).
  */
 int mlmq_server_create(const mlmq_graph* const* graphs, int32_t ngraphs, uint64_t mem_budget_bytes,
                        int32_t max_slots, const mlmq_config* cfg, mlmq_server** out);

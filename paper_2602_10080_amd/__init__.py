@@ -30,13 +30,16 @@ UNREACHABLE = 0xFFFFFFFF
 
 L1_NONE, L1_VEC, L1_NEARFAR, L1_FILTER, L1_SLF = 0, 1, 2, 3, 4
 RELAX_PRECHECK, RELAX_ATOMIC = 0, 1
-L2_FIFO, L2_BUCKET = 0, 1
+L2_FIFO, L2_BUCKET, L2_PQ = 0, 1, 2
 MEM_HOST, MEM_DEVICE = 0, 1
 
 # C-ABI entry points declared in include/mlmq.h
 EXPORTS = (
     "mlmq_config_default", "mlmq_graph_create", "mlmq_graph_destroy", "mlmq_graph_info", "mlmq_graph_config",
-    "mlmq_features_host", "mlmq_sssp", "mlmq_sssp_noalloc", "mlmq_bfs", "mlmq_check", "mlmq_sssp_batch", "mlmq_autotune", "mlmq_server_create",
+    "mlmq_features_host", "mlmq_sssp", "mlmq_sssp_noalloc", "mlmq_bfs", "mlmq_check", "mlmq_latency_probe",
+    "mlmq_sssp_batch",
+    "mlmq_candidate_count", "mlmq_candidate_config", "mlmq_select_inputs", "mlmq_select_rank", "mlmq_select",
+    "mlmq_autotune", "mlmq_server_create",
     "mlmq_server_submit", "mlmq_server_poll", "mlmq_server_wait", "mlmq_server_times",
     "mlmq_server_destroy", "mlmq_last_error",
 )
@@ -73,12 +76,12 @@ class Config(ctypes.Structure):
         ("th_hub", ctypes.c_uint32), ("hub_chunk", ctypes.c_uint32), ("wg_size", ctypes.c_uint32),
         ("grid_wgs", ctypes.c_uint32), ("l2_capacity", ctypes.c_uint64), ("stream", ctypes.c_void_p),
         ("timeout_ms", ctypes.c_uint32), ("max_retries", ctypes.c_uint32),
-        ("stats_out", ctypes.POINTER(Stats)),
+        ("stats_out", ctypes.POINTER(Stats)), ("donate_min", ctypes.c_uint32), ("pnum", ctypes.c_uint32),
     ]
 
     KNOBS = ("l0_rows", "l1_type", "l2_type", "relax_mode", "l1_cap", "l1_flush_wb", "delta1", "delta2_log2", "bmax",
              "bnum", "th_v", "th_hub", "hub_chunk", "wg_size", "grid_wgs", "l2_capacity", "timeout_ms",
-             "max_retries")
+             "max_retries", "donate_min", "pnum")
 
     def as_dict(self) -> dict:
         return {k: int(getattr(self, k)) for k in self.KNOBS}
@@ -113,7 +116,14 @@ def _declare(lib):
         "mlmq_sssp_noalloc": (ctypes.c_int, [vp, u32, vp, ctypes.POINTER(Config)]),
         "mlmq_bfs": (ctypes.c_int, [vp, u32, vp, ctypes.POINTER(Config)]),
         "mlmq_check": (ctypes.c_int, [vp, u32, vp, vp, ctypes.POINTER(u64), ctypes.POINTER(ctypes.c_float)]),
+        "mlmq_latency_probe": (ctypes.c_int, [vp, u32, u32, vp, ctypes.POINTER(ctypes.c_double),
+                                              ctypes.POINTER(ctypes.c_double)]),
         "mlmq_sssp_batch": (ctypes.c_int, [vp, vp, vp, i32, vp, vp]),
+        "mlmq_candidate_count": (i32, []),
+        "mlmq_candidate_config": (ctypes.c_int, [vp, i32, ctypes.POINTER(Config)]),
+        "mlmq_select_inputs": (ctypes.c_int, [ctypes.POINTER(Features), i32, ctypes.POINTER(ctypes.c_float)]),
+        "mlmq_select_rank": (ctypes.c_int, [ctypes.POINTER(Features), vp, vp, i32]),
+        "mlmq_select": (ctypes.c_int, [vp, ctypes.POINTER(Config)]),
         "mlmq_autotune": (ctypes.c_int, [vp, u32, ctypes.POINTER(Config)]),
         "mlmq_server_create": (ctypes.c_int, [vp, i32, u64, i32, ctypes.POINTER(Config), ctypes.POINTER(vp)]),
         "mlmq_server_submit": (ctypes.c_int, [vp, i32, u32, vp, ctypes.POINTER(u64)]),
@@ -306,6 +316,16 @@ def check(graph: Graph, source: int, dist, stream=None):
     return int(bad.value), float(ms.value)
 
 
+def latency_probe(graph: Graph, source: int, hops: int = 4096, stream=None):
+    """(ns per dependent relaxation hop, ns per hand-off between two
+    workgroups) measured on graph's device copy (mlmq_latency_probe)."""
+    hop = ctypes.c_double()
+    hand = ctypes.c_double()
+    _check(lib().mlmq_latency_probe(graph.handle, int(source), int(hops), _stream_handle(stream), ctypes.byref(hop),
+                                    ctypes.byref(hand)))
+    return float(hop.value), float(hand.value)
+
+
 def _single(fn: str, graph: Graph, source: int, out, config: Optional[Config], stream, stats: bool):
     if out is None:
         out = new_dist(graph.n)
@@ -366,11 +386,58 @@ def sssp_batch(graphs: Sequence[Graph], sources: Sequence[int], outs=None,
     return res
 
 
-def autotune(graph: Graph, budget_ms: int = 2000) -> Config:
-    """Empirical search over queue configurations; the winner is cached in the
-    library for this graph (used when no config is passed) and returned."""
+def autotune(graph: Graph, budget_ms: int = 2000, stream=None) -> Config:
+    """Times the feature-driven default and the selector's top templates; the
+    winner is cached in the library for this graph (used when no config is
+    passed) and returned."""
     c = default_config()
+    c.stream = _stream_handle(stream)
     _check(lib().mlmq_autotune(graph.handle, int(budget_ms), ctypes.byref(c)))
+    c.stream = None
+    return c
+
+
+def candidate_count() -> int:
+    return int(lib().mlmq_candidate_count())
+
+
+def candidate_config(graph: Graph, t: int) -> Config:
+    """Template t (or the feature-driven default for t = -1) as a config for graph."""
+    c = default_config()
+    _check(lib().mlmq_candidate_config(graph.handle, int(t), ctypes.byref(c)))
+    return c
+
+
+def _features_struct(f) -> Features:
+    if isinstance(f, Features):
+        return f
+    s = Features()
+    for k, _ in Features._fields_:
+        setattr(s, k, float(f[k]))
+    return s
+
+
+def select_inputs(f, t: int) -> np.ndarray:
+    """The selector's model inputs for template t on features f (host only)."""
+    x = (ctypes.c_float * 20)()
+    _check(lib().mlmq_select_inputs(ctypes.byref(_features_struct(f)), int(t), x))
+    return np.frombuffer(x, dtype=np.float32).copy()
+
+
+def select_rank(f) -> tuple:
+    """(template ids best first, predicted relative performance per template)
+    for features f (host only)."""
+    k = candidate_count()
+    order = np.empty(k, np.int32)
+    scores = np.empty(k, np.float32)
+    _check(lib().mlmq_select_rank(ctypes.byref(_features_struct(f)), order.ctypes.data, scores.ctypes.data, k))
+    return order, scores
+
+
+def select(graph: Graph) -> Config:
+    """The selector's top template for graph (nothing is timed or cached)."""
+    c = default_config()
+    _check(lib().mlmq_select(graph.handle, ctypes.byref(c)))
     return c
 
 

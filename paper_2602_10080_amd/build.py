@@ -1,14 +1,20 @@
-"""Compile the HIP library libmlmq.so for gfx950 with hipcc (in-tree)."""
+"""Compile the HIP library libmlmq.so for gfx950 with hipcc (in-tree).
+
+Each source is compiled to an object of its own (in parallel), then linked.
+"""
 from __future__ import annotations
 
 import glob
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmlmq.so")
+OBJ = os.path.join(ROOT, "_build", "mlmq_obj")
 ARCH = os.environ.get("MLMQ_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [
@@ -16,7 +22,6 @@ HIPCC_FLAGS = [
     "-O3",
     "-std=c++17",
     "-fPIC",
-    "-shared",
     # never form packed fp32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
@@ -29,11 +34,32 @@ def sources():
 
 def build(verbose: bool = False) -> str:
     """Always recompiles (the caller decides whether a build is needed)."""
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = ["hipcc", *HIPCC_FLAGS, *sources(), "-o", tmp]
+    os.makedirs(OBJ, exist_ok=True)
+    tag = "%d" % os.getpid()
+
+    def compile_one(src):
+        obj = os.path.join(OBJ, os.path.basename(src) + "." + tag + ".o")
+        cmd = ["hipcc", *HIPCC_FLAGS, "-c", src, "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.check_call(cmd)
+        return obj
+
+    srcs = sources()
+    # the kernel file takes longest: start it first
+    srcs.sort(key=lambda s: not s.endswith(".hip"))
+    with ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
+        objs = list(ex.map(compile_one, srcs))
+    tmp = LIB + ".tmp" + tag
+    cmd = ["hipcc", *HIPCC_FLAGS, "-shared", *objs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
-    subprocess.check_call(cmd)
+    try:
+        subprocess.check_call(cmd)
+    finally:
+        for o in objs:
+            if os.path.exists(o):
+                os.remove(o)
     os.replace(tmp, LIB)
     return LIB
 

@@ -96,7 +96,9 @@ int check_config(const mlmq_config* c) {
     return set_error(MLMQ_ERR_INVALID_ARG, "config struct_size %u != %zu", c->struct_size, sizeof(mlmq_config));
   if (c->l0_rows > kMaxL0Rows) return set_error(MLMQ_ERR_INVALID_ARG, "l0_rows must be 0..%d", kMaxL0Rows);
   if (c->l1_type > MLMQ_L1_SLF) return set_error(MLMQ_ERR_INVALID_ARG, "unknown l1_type %u", c->l1_type);
-  if (c->l2_type > MLMQ_L2_BUCKET) return set_error(MLMQ_ERR_INVALID_ARG, "unknown l2_type %u", c->l2_type);
+  if (c->l2_type > MLMQ_L2_PQ) return set_error(MLMQ_ERR_INVALID_ARG, "unknown l2_type %u", c->l2_type);
+  if (c->l2_type == MLMQ_L2_PQ && (c->pnum < 1 || c->pnum > 64))
+    return set_error(MLMQ_ERR_INVALID_ARG, "pnum must be in [1, 64]");
   if (c->relax_mode > MLMQ_RELAX_ATOMIC)
     return set_error(MLMQ_ERR_INVALID_ARG, "unknown relax_mode %u", c->relax_mode);
   if (c->l1_type != MLMQ_L1_NONE && (!is_pow2(c->l1_cap) || c->l1_cap < 64 || c->l1_cap > 8192))
@@ -113,6 +115,8 @@ int check_config(const mlmq_config* c) {
     return set_error(MLMQ_ERR_INVALID_ARG, "th_hub must be 0 or >= hub_chunk");
   if (c->wg_size != 64) return set_error(MLMQ_ERR_INVALID_ARG, "wg_size must be 64 (one wave per workgroup)");
   if (c->l2_capacity > (1ull << 34)) return set_error(MLMQ_ERR_INVALID_ARG, "l2_capacity too large");
+  if (c->donate_min && (c->donate_min < 16 || c->donate_min > 65536))
+    return set_error(MLMQ_ERR_INVALID_ARG, "donate_min must be 0 or in [16, 65536]");
   return MLMQ_OK;
 }
 
@@ -138,6 +142,7 @@ void default_config(mlmq_config* c) {
   c->l2_capacity = 0;
   c->timeout_ms = 60000;
   c->max_retries = 3;
+  c->pnum = 1;
   c->stats_out = keep_stats;
   c->stream = keep_stream;
 }
@@ -313,17 +318,21 @@ static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 // Queue memory of one query for a config.
 QueryPlan plan_query(const mlmq_graph* g, const mlmq_config& c, uint32_t extra_nb_log2, uint32_t hub_scale) {
   QueryPlan p;
-  p.nrings = c.l2_type == MLMQ_L2_BUCKET ? c.bmax : 1;
+  const bool pq = c.l2_type == MLMQ_L2_PQ;
+  p.nrings = c.l2_type == MLMQ_L2_BUCKET ? c.bmax : (pq ? c.pnum : 1);
   uint64_t cap = c.l2_capacity;
   if (!cap) {
     // FIFO: room for every vertex twice; buckets: a quarter of the vertices
-    // per ring (live elements concentrate in a few buckets at a time).
+    // per ring (live elements concentrate in a few buckets at a time);
+    // priority queues: every vertex twice over all of them.
     cap = c.l2_type == MLMQ_L2_BUCKET ? std::max<uint64_t>(g->n / 4, 1u << 14) : 2ull * g->n;
     cap = std::max<uint64_t>(cap, 1u << 16);
-  } else if (c.l2_type == MLMQ_L2_BUCKET) {
+    if (pq) cap = std::max<uint64_t>(cap / p.nrings, 1u << 12);
+  } else if (c.l2_type == MLMQ_L2_BUCKET || pq) {
     cap = std::max<uint64_t>(cap / p.nrings, 64);
   }
-  p.nb_log2 = log2_ceil((cap + 63) / 64) + extra_nb_log2;
+  // rings: 2^nb_log2 blocks; heaps: node 0 (partial buffer) + 2^nb_log2 - 1 tree nodes
+  p.nb_log2 = log2_ceil((cap + 63) / 64 + (pq ? 1 : 0)) + extra_nb_log2;
   p.nb_log2 = std::max<uint32_t>(p.nb_log2, 4);
   uint64_t hubs = c.th_hub ? count_degree_above(g, c.th_hub) : 0;
   p.hub_cap = c.th_hub ? (uint32_t)std::min<uint64_t>(std::max<uint64_t>(1024, 4 * hubs) * hub_scale, 1u << 26) : 1;
@@ -383,7 +392,7 @@ QueryDesc make_desc(const mlmq_graph* g, const mlmq_config& c, const QueryPlan& 
   // donation threshold: larger graphs carry larger frontiers per wave, and
   // handing work out early only adds global-queue round trips (grid2048:
   // 64 → 20.0 ms vs 22.0 ms with 32; grid512 and grid1024 best at 32)
-  d.donate_min = g->n >= (1 << 21) ? 64u : 32u;
+  d.donate_min = c.donate_min ? c.donate_min : (g->n >= (1 << 21) ? 64u : 32u);
   return d;
 }
 
@@ -479,7 +488,7 @@ void pool_trim() {
 
 // Launch shape for a config: workgroup size, LDS bytes and the number of
 // persistent workgroups that fit on the device at once.
-int launch_shape(const mlmq_config& c, uint32_t l1_cap, bool two, bool stage, LaunchShape* out) {
+int launch_shape(const mlmq_config& c, uint32_t l1_cap, bool two, bool stage, bool pq, LaunchShape* out) {
   const DeviceInfo* di = device_info();
   LaunchShape s;
   s.wg = c.wg_size;
@@ -487,12 +496,13 @@ int launch_shape(const mlmq_config& c, uint32_t l1_cap, bool two, bool stage, La
   s.l1_cap = l1_cap;
   s.two = two;
   s.stage = stage;
+  s.pq = pq;
   s.lds = worker_lds_bytes(s.waves, l1_cap, two, stage);
   if (s.lds > di->lds_per_wg)
     return set_error(MLMQ_ERR_INVALID_ARG, "L1 needs %zu bytes of LDS per workgroup (limit %zu)", s.lds,
                      di->lds_per_wg);
   int per_cu = 0;
-  hipError_t e = worker_occupancy(s.wg, s.lds, &per_cu);
+  hipError_t e = worker_occupancy(s.wg, s.lds, s.pq, &per_cu);
   if (e != hipSuccess) return hip_fail(e, "occupancy query");
   if (per_cu < 1) return set_error(MLMQ_ERR_INVALID_ARG, "workgroup shape does not fit on a CU");
   s.max_grid = (uint32_t)per_cu * (uint32_t)di->cus;
@@ -513,6 +523,7 @@ LaunchArgs make_args(const QueryDesc* d_desc, BatchCtrl* d_batch, int nq, const 
   a.l1_two = s.two ? 1u : 0u;
   a.stage = s.stage ? 1u : 0u;
   a.waves = s.waves;
+  a.pq = s.pq ? 1u : 0u;
   a.timeout_ticks = (uint64_t)(timeout_ms ? timeout_ms : 60000) * di->ticks_per_ms;
   a.cap_wait_ticks = 20ull * di->ticks_per_ms;
   a.beats = d_beats;
@@ -538,7 +549,10 @@ std::string describe_query_state(const QueryDesc& d, const uint32_t* d_beats, ui
     return "queue state unreadable";
   }
   uint64_t reserved = hc.hub_units.v;
-  for (const RingCtr& r : hr) reserved += r.tail.v;
+  if (d.l2_type == MLMQ_L2_PQ)
+    reserved += hc.pq_in.v;  // elements written to the priority queues
+  else
+    for (const RingCtr& r : hr) reserved += r.tail.v;
   char buf[256];
   snprintf(buf, sizeof(buf), "done %u reserved %llu cur %u hungry %u active %u hub %u/%u; tail/head:", hc.done.v,
            (unsigned long long)reserved, hc.cur.v, hc.hungry.v, hc.active.v, hc.hub_head.v, hc.hub_tail.v);
@@ -731,7 +745,8 @@ void heuristic_config(const mlmq_graph* g, mlmq_config* c) {
     den = 9;
   }
   LaunchShape s;
-  if (num != den && launch_shape(*c, c->l1_cap, c->l1_type == MLMQ_L1_NEARFAR, c->l2_type == MLMQ_L2_BUCKET, &s) ==
+  if (num != den && launch_shape(*c, c->l1_cap, c->l1_type == MLMQ_L1_NEARFAR, c->l2_type == MLMQ_L2_BUCKET,
+                                c->l2_type == MLMQ_L2_PQ, &s) ==
                         MLMQ_OK)
     c->grid_wgs = std::max<uint32_t>(64, s.max_grid * num / den);
   else
@@ -746,7 +761,7 @@ int run_single(const mlmq_graph* g, uint32_t source, uint32_t* dist_out, const m
   const bool dev_out = is_device_ptr(dist_out);
   LaunchShape shape;
   rc = launch_shape(c, c.l1_type == MLMQ_L1_NONE ? 64u : c.l1_cap, c.l1_type == MLMQ_L1_NEARFAR,
-                    c.l2_type == MLMQ_L2_BUCKET, &shape);
+                    c.l2_type == MLMQ_L2_BUCKET, c.l2_type == MLMQ_L2_PQ, &shape);
   if (rc) return rc;
   uint32_t extra = 0, hub_scale = 1, retries = 0;
   for (;;) {
@@ -768,7 +783,8 @@ int run_single(const mlmq_graph* g, uint32_t source, uint32_t* dist_out, const m
     QueryDesc* h_desc = reinterpret_cast<QueryDesc*>(static_cast<char*>(slab->host) + sizeof(QueryCtrl));
     *h_desc = make_desc(g, c, p, base, d_dist, source, shape.grid);
     h_desc->unit_w = unit_weights ? 1u : 0u;
-    if (unit_weights) h_desc->donate_min = 32u;  // breadth-first levels: early hand-out pays (grid2048 17.4 vs 19.4 ms)
+    // breadth-first levels: early hand-out pays (grid2048 17.4 vs 19.4 ms)
+    if (unit_weights && !c.donate_min) h_desc->donate_min = 32u;
     uint32_t* d_beats = reinterpret_cast<uint32_t*>(base + beats_off);
     LaunchArgs a = make_args(d_desc, d_batch, 1, shape, c.timeout_ms, d_beats);
     hipEvent_t ev0 = nullptr, evw = nullptr, ev1 = nullptr;
@@ -915,7 +931,7 @@ extern "C" int mlmq_sssp_noalloc(const mlmq_graph* g, uint32_t source, uint32_t*
   if (rc) return rc;
   LaunchShape shape;
   rc = launch_shape(c, c.l1_type == MLMQ_L1_NONE ? 64u : c.l1_cap, c.l1_type == MLMQ_L1_NEARFAR,
-                    c.l2_type == MLMQ_L2_BUCKET, &shape);
+                    c.l2_type == MLMQ_L2_BUCKET, c.l2_type == MLMQ_L2_PQ, &shape);
   if (rc) return rc;
   // Layout inside the array: queues, descriptor, launch control words, the
   // overflow flag and one heartbeat word per workgroup.
@@ -968,6 +984,39 @@ extern "C" int mlmq_sssp_noalloc(const mlmq_graph* g, uint32_t source, uint32_t*
   }
   fill_stats(c.stats_out, h_ctrl, 0.0, 0.0, shape.grid, 0);
   return rc;
+}
+
+extern "C" int mlmq_latency_probe(const mlmq_graph* g, uint32_t source, uint32_t hops, void* stream,
+                                  double* hop_ns_out, double* handoff_ns_out) {
+  if (!g || !hop_ns_out || !handoff_ns_out) return set_error(MLMQ_ERR_INVALID_ARG, "NULL argument");
+  if (source >= (uint32_t)g->n) return set_error(MLMQ_ERR_INVALID_ARG, "source %u >= n %d", source, g->n);
+  if (hops < 1 || hops > (1u << 24)) return set_error(MLMQ_ERR_INVALID_ARG, "hops must be in [1, 2^24]");
+  int rc = need_device();
+  if (rc) return rc;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  constexpr uint32_t kRounds = 2048;
+  const size_t lab_bytes = align_up(4ull * g->n, 256);
+  void* buf = nullptr;
+  hipError_t e = hipMalloc(&buf, lab_bytes + 256 + 64);
+  if (e != hipSuccess) return hip_fail(e, "probe scratch");
+  auto* lab = static_cast<uint32_t*>(buf);
+  auto* word = reinterpret_cast<uint32_t*>(static_cast<char*>(buf) + lab_bytes);
+  auto* d_out = reinterpret_cast<uint64_t*>(static_cast<char*>(buf) + lab_bytes + 256);
+  uint64_t h_out[4] = {0, 0, 0, 0};
+  e = hipMemsetAsync(lab, 0xFF, lab_bytes, s);
+  if (e == hipSuccess) e = hipMemsetAsync(word, 0, 256 + 64, s);
+  const uint64_t limit = 2000ull * device_info()->ticks_per_ms;  // 2 s
+  if (e == hipSuccess)
+    e = launch_latency_probes(g->d_off, g->d_adj, lab, (uint32_t)g->n, source, hops, word, kRounds, limit, d_out, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(h_out, d_out, sizeof(h_out), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(buf);
+  if (e != hipSuccess) return hip_fail(e, "latency probes");
+  if (h_out[3]) return set_error(MLMQ_ERR_TIMEOUT, "hand-off probe: the second workgroup did not answer");
+  const double ns_per_tick = 1e6 / (double)device_info()->ticks_per_ms;
+  *hop_ns_out = (double)h_out[0] * ns_per_tick / hops;
+  *handoff_ns_out = (double)h_out[2] * ns_per_tick / (2.0 * kRounds);
+  return MLMQ_OK;
 }
 
 extern "C" int mlmq_bfs(const mlmq_graph* g, uint32_t source, uint32_t* levels_out, const mlmq_config* cfg) {

@@ -60,6 +60,7 @@ struct LaunchShape {
   uint32_t wg = 256, waves = 4, l1_cap = 64, grid = 1, max_grid = 1;
   bool two = false;
   bool stage = false;
+  bool pq = false;  // kernel variant with the L2 priority-queue code
   size_t lds = 0;
 };
 
@@ -79,7 +80,7 @@ QueryDesc make_desc(const mlmq_graph* g, const mlmq_config& c, const QueryPlan& 
 int slab_acquire(size_t dev_bytes, size_t host_bytes, Slab** out);
 void slab_release(Slab* s);
 void pool_trim();
-int launch_shape(const mlmq_config& c, uint32_t l1_cap, bool two, bool stage, LaunchShape* out);
+int launch_shape(const mlmq_config& c, uint32_t l1_cap, bool two, bool stage, bool pq, LaunchShape* out);
 LaunchArgs make_args(const QueryDesc* d_desc, BatchCtrl* d_batch, int nq, const LaunchShape& s, uint32_t timeout_ms,
                      uint32_t* d_beats);
 int status_to_code(uint32_t st);

@@ -1,5 +1,4 @@
-// Batched solves in one persistent, hipGraph-captured launch, and the
-// empirical autotuner.
+// Batched solves in one persistent, hipGraph-captured launch.
 
 #include <hip/hip_runtime.h>
 
@@ -63,14 +62,15 @@ extern "C" int mlmq_sssp_batch(const mlmq_graph* const* graphs, const uint32_t* 
   mlmq_config lc = conf[0];
   lc.grid_wgs = 0;
   uint32_t l1cap = 64;
-  bool two = false, stage = false;
+  bool two = false, stage = false, pq = false;
   for (auto& c : conf) {
     if (c.l1_type != MLMQ_L1_NONE) l1cap = std::max(l1cap, c.l1_cap);
     two = two || c.l1_type == MLMQ_L1_NEARFAR;
     stage = stage || c.l2_type == MLMQ_L2_BUCKET;
+    pq = pq || c.l2_type == MLMQ_L2_PQ;
   }
   LaunchShape shape;
-  rc = launch_shape(lc, l1cap, two, stage, &shape);
+  rc = launch_shape(lc, l1cap, two, stage, pq, &shape);
   if (rc) return rc;
   hipStream_t stream = lc.stream ? reinterpret_cast<hipStream_t>(lc.stream) : internal_stream();
   // Largest queries first, so the long ones start early (LPT order).
@@ -197,160 +197,4 @@ extern "C" int mlmq_sssp_batch(const mlmq_graph* const* graphs, const uint32_t* 
   }
   if (first_bad != MLMQ_OK) set_error(first_bad, "at least one query of the batch failed");
   return first_bad;
-}
-
-// ------------------------------------------------------------ autotuner
-
-namespace {
-
-// Candidate configurations, pruned by the Table 2 features with the
-// insights of Section 3.5: power-law graphs are sensitive to priority
-// inversion (priority-aware L1/L2 first); meshes and roads are not, and
-// smaller graphs favour parallel FIFO queues.
-std::vector<mlmq_config> candidates(const mlmq_graph* g) {
-  mlmq_config base;
-  base.struct_size = sizeof(mlmq_config);
-  default_config(&base);
-  heuristic_config(g, &base);
-  const mlmq_features& f = g->features;
-  const bool skewed = f.max_deg > 64 && f.std_deg > f.avg_deg;
-  const uint32_t mw = (uint32_t)std::max(1.0, f.avg_w);
-  uint32_t l2mw = 0;
-  while ((2u << l2mw) <= mw) ++l2mw;
-  std::vector<mlmq_config> out;
-  // share = num / 9 of the resident waves (9 = all)
-  auto add = [&](uint8_t l0, uint8_t l1, uint8_t l2, uint32_t d1, uint32_t d2l, uint32_t num9) {
-    mlmq_config c = base;
-    c.l0_rows = l0;
-    c.l1_type = l1;
-    c.l2_type = l2;
-    c.delta1 = std::max<uint32_t>(1, d1);
-    c.delta2_log2 = d2l;
-    c.grid_wgs = 0;
-    if (num9 < 9) {
-      LaunchShape s;
-      if (launch_shape(c, l1 == MLMQ_L1_NONE ? 64u : c.l1_cap, l1 == MLMQ_L1_NEARFAR, l2 == MLMQ_L2_BUCKET, &s) ==
-          MLMQ_OK)
-        c.grid_wgs = std::max<uint32_t>(64, s.max_grid * num9 / 9);
-      else
-        (void)hipGetLastError();
-    }
-    out.push_back(c);
-  };
-  out.push_back(base);
-  if (skewed) {
-    // L1 capacity x launch size around the feature-driven default, then the
-    // other queue families at the default size
-    const uint32_t g0 = base.grid_wgs ? base.grid_wgs : 1024;
-    for (uint32_t cap : {128u, 256u, 512u})
-      for (uint32_t g : {g0 / 2, g0, g0 + g0 / 2}) {
-        mlmq_config c = base;
-        c.l1_cap = cap;
-        c.grid_wgs = std::max<uint32_t>(64, g);
-        out.push_back(c);
-      }
-    mlmq_config v = base;
-    v.l1_type = MLMQ_L1_VEC;
-    v.l1_flush_wb = 8;
-    out.push_back(v);
-    mlmq_config slf = base;
-    slf.l1_type = MLMQ_L1_SLF;
-    out.push_back(slf);
-    slf.l0_rows = 2;
-    out.push_back(slf);
-    mlmq_config dq = base;
-    dq.l2_type = MLMQ_L2_BUCKET;
-    dq.delta2_log2 = l2mw > 0 ? l2mw - 1 : 0;
-    dq.delta1 = std::max<uint32_t>(1, mw / 4);
-    out.push_back(dq);
-  } else {
-    for (uint32_t share : {1u, 2u, 3u, 6u}) {
-      add(0, MLMQ_L1_NEARFAR, MLMQ_L2_FIFO, 2 * mw, l2mw, share);
-      add(0, MLMQ_L1_NEARFAR, MLMQ_L2_BUCKET, mw, l2mw + 2, share);
-    }
-    add(0, MLMQ_L1_NEARFAR, MLMQ_L2_FIFO, mw, l2mw, 2);
-    add(0, MLMQ_L1_NEARFAR, MLMQ_L2_BUCKET, 2 * mw, l2mw + 3, 3);
-  }
-  return out;
-}
-
-}  // namespace
-
-extern "C" int mlmq_autotune(mlmq_graph* g, uint32_t budget_ms, mlmq_config* out) {
-  if (!g) return set_error(MLMQ_ERR_INVALID_ARG, "graph is NULL");
-  int rc = need_device();
-  if (rc) return rc;
-  if (!budget_ms) budget_ms = 2000;
-  uint32_t* d_dist = nullptr;
-  hipError_t e = hipMalloc(&d_dist, 4ull * g->n);
-  if (e != hipSuccess) return hip_fail(e, "autotune buffer");
-  // Seeded sources: the highest-degree vertex plus two spread by a fixed LCG
-  // among vertices with out-degree >= 1 (located on the host copy of offsets).
-  std::vector<int32_t> off((size_t)g->n + 1);
-  e = hipMemcpy(off.data(), g->d_off, 4ull * (g->n + 1), hipMemcpyDeviceToHost);
-  if (e != hipSuccess) {
-    (void)hipFree(d_dist);
-    return hip_fail(e, "autotune offsets");
-  }
-  std::vector<uint32_t> srcs;
-  int32_t best_v = 0, best_d = -1;
-  for (int32_t u = 0; u < g->n; ++u)
-    if (off[u + 1] - off[u] > best_d) {
-      best_d = off[u + 1] - off[u];
-      best_v = u;
-    }
-  srcs.push_back((uint32_t)best_v);
-  uint64_t x = 0x2545F4914F6CDD1Dull;
-  for (int tries = 0; srcs.size() < 3 && tries < 1000; ++tries) {
-    x = x * 6364136223846793005ull + 1442695040888963407ull;
-    const uint32_t u = (uint32_t)((x >> 33) % (uint64_t)g->n);
-    if (off[u + 1] > off[u]) srcs.push_back(u);
-  }
-  const auto t0 = std::chrono::steady_clock::now();
-  std::vector<mlmq_config> cand = candidates(g);
-  double best_ms = 1e300;
-  mlmq_config best = cand[0];
-  for (size_t ci = 0; ci < cand.size(); ++ci) {
-    const double el =
-        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-    if (ci > 0 && el > budget_ms) break;
-    mlmq_config c = cand[ci];
-    mlmq_stats st;
-    std::memset(&st, 0, sizeof(st));
-    st.struct_size = sizeof(st);
-    c.stats_out = &st;
-    c.stream = out ? out->stream : nullptr;
-    // a poor candidate may not take more than the whole budget
-    c.timeout_ms = std::min<uint32_t>(c.timeout_ms ? c.timeout_ms : 60000, std::max<uint32_t>(200, budget_ms));
-    c.max_retries = 1;
-    double total = 0;
-    bool okc = true;
-    for (uint32_t s : srcs) {
-      if (run_single(g, s, d_dist, c) != MLMQ_OK) {
-        okc = false;
-        break;
-      }
-      total += st.kernel_ms;
-    }
-    if (okc && total < best_ms) {
-      best_ms = total;
-      best = cand[ci];
-    }
-  }
-  (void)hipFree(d_dist);
-  best.stats_out = nullptr;
-  best.stream = nullptr;
-  {
-    std::lock_guard<std::mutex> lk(g->mu);
-    g->tuned = best;
-    g->has_tuned = true;
-  }
-  if (out) {
-    mlmq_stats* so = out->stats_out;
-    void* ss = out->stream;
-    *out = best;
-    out->stats_out = so;
-    out->stream = ss;
-  }
-  return MLMQ_OK;
 }

@@ -62,10 +62,12 @@ struct QueryCtrl {
   Word finished;   // workgroups that left this query
   Word hungry;     // waves of this query that currently find no work
   Word active;     // waves currently working on this query
+  Word pq_in;      // elements written to the L2 priority queues (termination count)
   uint64_t stats[16];  // [0, kNumCounters) used
 };
 
 // L2 ring counters: tickets handed to writers (tail) and readers (head).
+// For the L2 priority queues, tail holds the number of heap nodes in use.
 struct RingCtr {
   Word tail;
   Word head;
@@ -79,7 +81,8 @@ struct QueryDesc {
   uint32_t* dist;      // output distances [n]
   QueryCtrl* ctrl;
   RingCtr* rings;      // [nrings]
-  uint64_t* hdr;       // [nrings << nb_log2] block headers: (seq << 32) | count
+  uint64_t* hdr;       // [nrings << nb_log2] block headers: (seq << 32) | count;
+                       // priority queues: node words, lock (low 32 bits) and state (high)
   uint64_t* data;      // [(nrings << nb_log2) * 64] elements: v | (d << 32)
   uint64_t* hub_rec;   // [2 * hub_cap] records: (v | d << 32), (beg | end << 32)
   uint32_t* hub_cur;   // [hub_cap] chunk claim cursors
@@ -87,7 +90,7 @@ struct QueryDesc {
   uint32_t n;
   uint32_t source;
   uint32_t nb_log2;    // blocks per ring = 1 << nb_log2
-  uint32_t nrings;     // 1 (FIFO) or bmax (bucket)
+  uint32_t nrings;     // 1 (FIFO), bmax (bucket) or pnum (priority queues)
   uint32_t hub_cap;
   uint32_t l0_cap;     // L0 elements per wave (rows * 64), 0 = off
   uint32_t l1_type;
@@ -120,6 +123,7 @@ struct LaunchArgs {
   uint32_t l1_two;     // 1 if a second (far) ring is allocated
   uint32_t stage;      // 1 if the bucket-queue write-combining area is allocated
   uint32_t waves;      // waves per workgroup (always 1)
+  uint32_t pq;         // 1: the kernel variant with the L2 priority-queue code
   uint64_t timeout_ticks;   // device watchdog (wall-clock ticks)
   uint64_t cap_wait_ticks;  // longest wait for a free L2 slot before overflow
   uint32_t* beats;          // [grid] last program point of each wave (nullable)
@@ -141,6 +145,7 @@ struct ServerArgs {
   uint32_t l1_cap;         // LDS ring capacity the launch was sized for
   uint32_t l1_two;         // 1 if a second (far) ring is allocated
   uint32_t stage;          // 1 if the bucket-queue write-combining area is allocated
+  uint32_t pq;             // 1: the kernel variant with the L2 priority-queue code
   uint64_t timeout_ticks;  // per-query device watchdog from the moment a wave joins
   uint64_t cap_wait_ticks;
   uint64_t idle_exit_ticks;  // a wave with no work for this long leaves the kernel
@@ -173,7 +178,7 @@ hipError_t launch_init(const QueryDesc* d_queries, BatchCtrl* d_batch, int nq, u
 hipError_t launch_worker(const LaunchArgs& a, uint32_t grid, uint32_t wg_size, size_t lds, hipStream_t s);
 hipError_t launch_overflow_check(const QueryDesc* d_query, uint32_t* d_flag, hipStream_t s);
 hipError_t launch_gather(const QueryDesc* d_queries, int nq, QueryResult* d_out, hipStream_t s);
-hipError_t worker_occupancy(uint32_t wg_size, size_t lds, int* wgs_per_cu);
+hipError_t worker_occupancy(uint32_t wg_size, size_t lds, bool pq, int* wgs_per_cu);
 hipError_t launch_server_worker(const ServerArgs& a, uint32_t grid, size_t lds, hipStream_t s);
 // Resets the query's memory, stores its descriptor in *d_slot, then stores
 // word into *d_join (two kernels in stream order).
@@ -185,7 +190,14 @@ hipError_t launch_server_signal(uint32_t* d_word, uint32_t v, hipStream_t s);
 hipError_t launch_check(const int32_t* off, const uint64_t* adj, const uint32_t* dist, uint32_t n, uint32_t m,
                         uint32_t source, uint8_t* tight, unsigned long long* bad, hipEvent_t ev0, hipEvent_t ev1,
                         hipStream_t s);
-hipError_t server_occupancy(size_t lds, int* wgs_per_cu);
+hipError_t server_occupancy(size_t lds, bool pq, int* wgs_per_cu);
+// Latency probes: a dependent-hop chain of `hops` relaxations from v0 over
+// labels lab[n] (out[0] = ticks), then `rounds` hand-off round trips between
+// two workgroups on *word (out[2] = ticks, out[3] = 1 if it gave up); word
+// and out must be zero on entry.
+hipError_t launch_latency_probes(const int32_t* off, const uint64_t* adj, uint32_t* lab, uint32_t n, uint32_t v0,
+                                 uint32_t hops, uint32_t* word, uint32_t rounds, uint64_t limit_ticks, uint64_t* out,
+                                 hipStream_t s);
 
 // Bytes of the fixed device array behind the allocation-free solve.
 constexpr size_t kNoAllocScratchBytes = 128ull << 20;

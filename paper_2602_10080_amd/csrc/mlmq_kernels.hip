@@ -8,7 +8,9 @@
 //       to its wave like the paper's per-warp L1 and needs no lock;
 //   L2  per query, in HBM: block-based FIFO ring(s) with ticket counters
 //       (Section 4.2), one ring for L2V or bmax rings used as Delta buckets
-//       for L2DQ.
+//       for L2DQ; or pnum batched heaps with per-node locks (L2PQ, and the
+//       multi-queue L2MPQ for pnum > 1), compiled into a second kernel
+//       variant only.
 // The worker only talks to the unified Read/Write cascade (Section 3.2-3.3):
 // Read takes from L0, else L1, else the global levels; Write appends to L0,
 // whose overflow moves everything to L1, whose overflow goes to L2.
@@ -141,6 +143,8 @@ struct Ctx {
   uint32_t l0h, l0n;         // L0 head position and count
   uint32_t* beat;            // this wave's heartbeat word (nullable)
   uint32_t it;               // loop iterations (heartbeat)
+  bool pq;                   // the query's L2 is the priority queue(s) (PQ kernel variant only)
+  uint32_t rq, wq;           // priority queues: this wave's reading queue, next queue written
   bool stop;                 // leave the query (terminated or failed)
   bool ovf;                  // a candidate distance overflowed
   bool hungry;               // this wave is counted in ctrl->hungry
@@ -284,6 +288,312 @@ __device__ __forceinline__ bool l2_put_block(Ctx& c, uint32_t ring, uint64_t e, 
   return true;
 }
 
+// ------------------------------------------------------------ L2 priority queues (L2PQ / L2MPQ)
+//
+// Section 4.2's warp-level priority queue in the spirit of a batched heap:
+// a complete binary tree of nodes, each holding a sorted batch of 64
+// elements, every node with its own lock; a node's elements are no larger
+// than its children's when no operation is passing through. The batch of a
+// node is read and written by the whole wave (lane i holds element i) and
+// batches are combined by bitonic merges across lanes. Node 0 of a queue is
+// a partial buffer of fewer than 64 elements; it, the node count and node 1
+// are guarded by node 1's lock.
+//   Write: merge the new elements into the partial buffer; once it reaches 64,
+//     its 64 smallest go down the tree: the node count grows by one (the
+//     new last node is marked as the target), and the batch is merged into
+//     each node on the path from the root to the target, each keeping its
+//     smaller half, locks taken parent before child (hand over hand).
+//   Read: the root's batch merged with the partial buffer gives the 64
+//     smallest elements; the last node's batch (waiting, with the root held,
+//     until an insertion on its way there has arrived) replaces the root and
+//     sinks: at each node the two children are merged, the child with the
+//     larger maximum keeps the larger half, and the node keeps the smallest
+//     64 of itself and the smaller half while the other child takes the rest
+//     and the descent continues there.
+// Every lock is taken in tree order (a parent before its children, the left
+// child before the right), so waits cannot form a cycle; the only other wait,
+// a reader holding the root for an insertion on its way to the last node,
+// waits for a wave that needs no lock above that node. All waits are bounded
+// by the watchdog and the cancel flag. Termination counts elements: pq_in
+// grows by k before k elements are written, done by the elements read.
+// L2MPQ (pnum > 1, after the multi-queue designs the paper cites): each wave
+// reads from queue blockIdx mod pnum and writes to the queues in turn,
+// starting at its reading queue; a wave whose reading queue is empty tries
+// the others once before it counts as idle, so no element is left in a queue
+// whose readers are busy elsewhere.
+
+constexpr uint64_t kKeyInf = ~0ull;
+enum : uint32_t { kNodeEmpty = 0, kNodeFull = 1, kNodeTarget = 2 };
+
+__device__ __forceinline__ uint64_t shfl64(uint64_t x, uint32_t src) {
+  const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)x, (int)src);
+  const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(x >> 32), (int)src);
+  return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+__device__ __forceinline__ uint64_t shfl_xor64(uint64_t x, uint32_t m) { return shfl64(x, lane() ^ m); }
+__device__ __forceinline__ uint64_t min64(uint64_t a, uint64_t b) { return a < b ? a : b; }
+__device__ __forceinline__ uint64_t max64(uint64_t a, uint64_t b) { return a < b ? b : a; }
+
+// Ascending bitonic sort of the wave's 64 keys (lane i ends with the i-th smallest).
+__device__ __forceinline__ uint64_t sort64(uint64_t x) {
+#pragma unroll
+  for (uint32_t k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+    for (uint32_t j = k >> 1; j; j >>= 1) {
+      const uint64_t y = shfl_xor64(x, j);
+      const bool up = (lane() & k) == 0u || k == 64u;
+      const bool low = (lane() & j) == 0u;
+      x = (low == up) ? min64(x, y) : max64(x, y);
+    }
+  }
+  return x;
+}
+
+// Sorts a bitonic sequence held one key per lane into ascending order.
+__device__ __forceinline__ uint64_t bitonic_clean(uint64_t x) {
+#pragma unroll
+  for (uint32_t j = 32; j; j >>= 1) {
+    const uint64_t y = shfl_xor64(x, j);
+    x = (lane() & j) == 0u ? min64(x, y) : max64(x, y);
+  }
+  return x;
+}
+
+// Merge of two ascending batches: lo gets the 64 smallest of the 128 keys,
+// hi the 64 largest, both ascending.
+__device__ __forceinline__ void merge64(uint64_t a, uint64_t b, uint64_t& lo, uint64_t& hi) {
+  const uint64_t br = shfl64(b, 63u - lane());
+  lo = bitonic_clean(min64(a, br));
+  hi = bitonic_clean(max64(a, br));
+}
+
+__device__ __forceinline__ uint64_t* pq_word(const Ctx& c, uint32_t q, uint32_t i) {
+  return c.q.hdr + (((uint64_t)q << c.q.nb_log2) + i);
+}
+__device__ __forceinline__ uint32_t* pq_lock(const Ctx& c, uint32_t q, uint32_t i) {
+  return reinterpret_cast<uint32_t*>(pq_word(c, q, i));
+}
+__device__ __forceinline__ uint32_t* pq_state(const Ctx& c, uint32_t q, uint32_t i) {
+  return reinterpret_cast<uint32_t*>(pq_word(c, q, i)) + 1;
+}
+__device__ __forceinline__ uint64_t* pq_keys(const Ctx& c, uint32_t q, uint32_t i) {
+  return c.q.data + ((((uint64_t)q << c.q.nb_log2) + i) << 6);
+}
+__device__ __forceinline__ uint64_t pq_load(const Ctx& c, uint32_t q, uint32_t i) {
+  return ld64(pq_keys(c, q, i) + lane());
+}
+__device__ __forceinline__ void pq_store(const Ctx& c, uint32_t q, uint32_t i, uint64_t x) {
+  st64(pq_keys(c, q, i) + lane(), x);
+}
+
+// Bounded wait for a node lock (false: the query failed meanwhile, or, with
+// tries != 0, the lock stayed busy for that many looks). The lock word is
+// read first and swapped only when it looks free, and the pause between looks
+// grows, so thousands of waiting waves do not flood the root's lock with
+// atomics (which would delay the holder's own release behind them).
+__device__ __forceinline__ bool pq_acquire(Ctx& c, uint32_t* lk, uint32_t tries = 0) {
+  for (uint32_t spins = 0;; ++spins) {
+    uint32_t got = 0;
+    if (lane() == 0) got = (ld32(lk) == 0u && cas32(lk, 0u, 1u)) ? 1u : 0u;
+    if (lane_val(got, 0)) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      return true;
+    }
+    if (tries && spins + 1u >= tries) return false;
+    if ((spins & 15u) == 15u && must_stop(c)) {
+      c.stop = true;
+      return false;
+    }
+    backoff(min(spins >> 1, 6u));
+  }
+}
+// Stores of the node's data complete before its lock is free again.
+__device__ __forceinline__ void pq_release(uint32_t* lk) {
+  vm_drain();
+  if (lane() == 0) __hip_atomic_store(lk, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Sinks the batch x just placed at node i (locked by the caller) until the
+// heap order holds below it; releases every lock it took.
+__device__ __forceinline__ void pq_sink(Ctx& c, uint32_t q, uint32_t i, uint64_t x) {
+  const uint32_t cap = (1u << c.q.nb_log2) - 1u;
+  for (;;) {
+    const uint32_t l = 2u * i, r = l + 1u;
+    bool hl = false, hr = false;
+    if (l <= cap) {
+      if (!pq_acquire(c, pq_lock(c, q, l))) return;
+      hl = uni(ld32(pq_state(c, q, l))) == kNodeFull;
+      if (!hl) pq_release(pq_lock(c, q, l));
+    }
+    if (r <= cap) {
+      if (!pq_acquire(c, pq_lock(c, q, r))) return;
+      hr = uni(ld32(pq_state(c, q, r))) == kNodeFull;
+      if (!hr) pq_release(pq_lock(c, q, r));
+    }
+    if (!hl && !hr) {
+      pq_release(pq_lock(c, q, i));
+      return;
+    }
+    uint32_t keep = 0, next = 0;  // child given its final batch, child the descent continues in
+    uint64_t small;
+    if (hl && hr) {
+      const uint64_t a = pq_load(c, q, l), b = pq_load(c, q, r);
+      uint64_t lo, hi;
+      merge64(a, b, lo, hi);
+      const bool left_big = shfl64(a, 63) >= shfl64(b, 63);
+      keep = left_big ? l : r;
+      next = left_big ? r : l;
+      pq_store(c, q, keep, hi);
+      pq_release(pq_lock(c, q, keep));
+      small = lo;
+    } else {
+      next = hl ? l : r;
+      small = pq_load(c, q, next);
+    }
+    if (shfl64(x, 63) <= shfl64(small, 0)) {  // already in order
+      if (hl && hr) pq_store(c, q, next, small);
+      pq_release(pq_lock(c, q, next));
+      pq_release(pq_lock(c, q, i));
+      return;
+    }
+    uint64_t lo, hi;
+    merge64(x, small, lo, hi);
+    pq_store(c, q, i, lo);
+    pq_store(c, q, next, hi);
+    pq_release(pq_lock(c, q, i));
+    i = next;
+    x = hi;
+  }
+}
+
+// Inserts a full sorted batch into queue q; the caller holds the root lock,
+// which this releases (with every other lock it takes).
+__device__ __forceinline__ void pq_push_full(Ctx& c, uint32_t q, uint64_t x) {
+  uint32_t* size = &c.q.rings[q].tail.v;
+  const uint32_t cap = (1u << c.q.nb_log2) - 1u;
+  const uint32_t tgt = uni(ld32(size)) + 1u;
+  if (tgt > cap) {
+    pq_release(pq_lock(c, q, 1));
+    fail(c, kStCapacity);
+    return;
+  }
+  if (lane() == 0) {
+    st32(size, tgt);
+    st32(pq_state(c, q, tgt), tgt == 1u ? kNodeFull : kNodeTarget);
+  }
+  uint32_t i = 1;
+  for (;;) {
+    if (i == tgt) {
+      pq_store(c, q, i, x);
+      vm_drain();
+      if (lane() == 0) st32(pq_state(c, q, i), kNodeFull);
+      pq_release(pq_lock(c, q, i));
+      return;
+    }
+    uint64_t lo, hi;
+    merge64(pq_load(c, q, i), x, lo, hi);
+    pq_store(c, q, i, lo);
+    x = hi;
+    // the child of i on the path to tgt
+    const uint32_t below = (31u - (uint32_t)__clz(tgt)) - (31u - (uint32_t)__clz(i));
+    const uint32_t next = tgt >> (below - 1u);
+    if (!pq_acquire(c, pq_lock(c, q, next))) return;
+    pq_release(pq_lock(c, q, i));
+    i = next;
+  }
+}
+
+// L2 Write to the priority queues.
+__device__ __forceinline__ void pq_write(Ctx& c, uint64_t e, bool ok) {
+  const uint32_t k = popc(ballot(ok));
+  if (!k) return;
+  const uint64_t x = sort64(ok ? e : kKeyInf);
+  const uint32_t q = c.wq;
+  c.wq = c.wq + 1u == c.q.nrings ? 0u : c.wq + 1u;
+  if (lane() == 0) add32(&c.q.ctrl->pq_in.v, k);  // reserved before it can be read
+  if (!pq_acquire(c, pq_lock(c, q, 1))) return;
+  const uint32_t p = uni(ld32(pq_state(c, q, 0)));
+  const uint64_t part = lane() < p ? pq_load(c, q, 0) : kKeyInf;
+  uint64_t lo, hi;
+  merge64(part, x, lo, hi);
+  const uint32_t t = p + k;
+  if (t < 64u) {
+    if (lane() < t) pq_store(c, q, 0, lo);
+    vm_drain();
+    if (lane() == 0) st32(pq_state(c, q, 0), t);
+    pq_release(pq_lock(c, q, 1));
+    return;
+  }
+  if (lane() < t - 64u) pq_store(c, q, 0, hi);
+  vm_drain();
+  if (lane() == 0) st32(pq_state(c, q, 0), t - 64u);
+  pq_push_full(c, q, lo);
+  c.ct[kCtL2Writes] += 1;
+}
+
+// Takes up to 64 of the smallest elements of queue q (false: it was empty).
+__device__ __forceinline__ bool pq_pop(Ctx& c, uint32_t q, uint64_t& e, bool& ok) {
+  // a cheap look before taking the root lock
+  const uint32_t size0 = uni(ld32(&c.q.rings[q].tail.v));
+  const uint32_t p0 = uni(ld32(pq_state(c, q, 0)));
+  if (size0 == 0u && p0 == 0u) return false;
+  // a reader that finds the root busy for a while moves on (another queue,
+  // or an idle turn) instead of queueing behind the writers
+  if (!pq_acquire(c, pq_lock(c, q, 1), 6u)) return false;
+  uint32_t* size = &c.q.rings[q].tail.v;
+  const uint32_t n = uni(ld32(size));
+  const uint32_t p = uni(ld32(pq_state(c, q, 0)));
+  const uint64_t part = lane() < p ? pq_load(c, q, 0) : kKeyInf;
+  if (n == 0u) {
+    if (lane() == 0) st32(pq_state(c, q, 0), 0u);
+    pq_release(pq_lock(c, q, 1));
+    ok = lane() < p;
+    e = part;
+    return p != 0u;
+  }
+  uint64_t lo, hi;
+  merge64(pq_load(c, q, 1), part, lo, hi);
+  e = lo;
+  ok = true;
+  if (lane() < p) pq_store(c, q, 0, hi);
+  if (n == 1u) {
+    if (lane() == 0) {
+      st32(size, 0u);
+      st32(pq_state(c, q, 1), kNodeEmpty);
+    }
+    pq_release(pq_lock(c, q, 1));
+    return true;
+  }
+  // wait, holding the root, until an insertion on its way to the last node
+  // has arrived there, then move that node's batch to the root
+  for (uint32_t spins = 0; uni(ld32(pq_state(c, q, n))) != kNodeFull; ++spins) {
+    if ((spins & 63u) == 63u && must_stop(c)) {
+      c.stop = true;
+      return true;  // the query is over; the elements are never counted done
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+  if (!pq_acquire(c, pq_lock(c, q, n))) return true;
+  const uint64_t last = pq_load(c, q, n);
+  if (lane() == 0) st32(pq_state(c, q, n), kNodeEmpty);
+  pq_release(pq_lock(c, q, n));
+  if (lane() == 0) st32(size, n - 1u);
+  pq_store(c, q, 1, last);
+  pq_sink(c, q, 1, last);
+  c.ct[kCtL2Reads] += 1;
+  return true;
+}
+
+// L2 Read from the priority queues: the wave's reading queue, then the others.
+__device__ __forceinline__ bool pq_read(Ctx& c, uint64_t& e, bool& ok) {
+  const uint32_t nq = c.q.nrings;
+  for (uint32_t j = 0; j < nq && !c.stop; ++j) {
+    const uint32_t q = c.rq + j < nq ? c.rq + j : c.rq + j - nq;
+    if (pq_pop(c, q, e, ok)) return !c.stop;
+  }
+  return false;
+}
+
 // Ring of absolute bucket b seen from head bucket cur: bucket index relative
 // to the head, clamped into [0, bmax - 1] (Section 4.2, L2DQ).
 __device__ __forceinline__ uint32_t bucket_ring(const Ctx& c, uint32_t cur, uint32_t b) {
@@ -336,6 +646,10 @@ __device__ __forceinline__ void stage_flush_all(Ctx& c) {
 // L2 Write of a lane vector.
 __device__ __forceinline__ void l2_write(Ctx& c, uint64_t e, bool ok) {
   if (!ballot(ok)) return;
+  if (c.pq) {
+    pq_write(c, e, ok);
+    return;
+  }
   if (c.q.nrings == 1) {
     l2_put_block(c, 0, e, ok, ballot(ok));
     return;
@@ -458,6 +772,7 @@ __device__ __forceinline__ void defer_later(Ctx& c, uint32_t cur, uint32_t j, ui
 
 // L2 Read.
 __device__ __forceinline__ bool l2_read(Ctx& c, uint64_t& e, bool& ok) {
+  if (c.pq) return pq_read(c, e, ok);
   if (c.q.nrings == 1) {
     uint32_t t = 0, h = 0;
     if (lane_val(c.pend, 0) == kInf) {
@@ -945,7 +1260,9 @@ __device__ __forceinline__ bool try_terminate(Ctx& c) {
   QueryCtrl* ctl = c.q.ctrl;
   const uint32_t done = uni(ld32(&ctl->done.v));
   vm_drain();
-  const uint32_t t = lane() < c.q.nrings ? ld32(&c.q.rings[lane()].tail.v) : 0u;
+  // reservations: ring tickets (blocks), or elements written to the priority queues
+  const uint32_t t = c.pq ? (lane() == 0 ? ld32(&ctl->pq_in.v) : 0u)
+                          : (lane() < c.q.nrings ? ld32(&c.q.rings[lane()].tail.v) : 0u);
   const uint32_t units = c.q.th_hub ? uni(ld32(&ctl->hub_units.v)) : 0u;
   const uint32_t reserved = uni(wave_sum(t)) + units;
   if (done == reserved) {
@@ -1006,7 +1323,7 @@ __device__ __forceinline__ void run_query(Ctx& c) {
       got = l2_read(c, e, ok);
       if (got) {
         set_hungry(c, false);
-        c.done_acc += 1u;
+        c.done_acc += c.pq ? popc(ballot(ok)) : 1u;  // elements (priority queues) or one block
         refill_threshold(c, uni(wave_min(ok ? elem_d(e) : kInf)));
       } else {
         // Idle: the wave holds nothing, so its delayed count can go out.
@@ -1061,8 +1378,14 @@ __device__ __forceinline__ uint32_t pick_query(const LaunchArgs& a) {
 // clearing, only their counters), no pending tickets, no counters.
 __device__ __forceinline__ void setup_ctx(Ctx& c, const QueryDesc& q, uint64_t* smem, uint32_t l1_cap_alloc,
                                           uint32_t two_alloc, uint32_t stage_alloc, const uint32_t* cancel,
-                                          uint64_t deadline, uint64_t cap_wait, uint32_t* beat_word) {
+                                          uint64_t deadline, uint64_t cap_wait, uint32_t* beat_word, bool pq_kernel) {
   c.q = q;
+  // pq_kernel is a literal at each kernel, so the ring-only variant drops
+  // every priority-queue branch; the host launches the priority-queue
+  // variant whenever a query of the launch uses priority queues
+  c.pq = pq_kernel && q.l2_type == MLMQ_L2_PQ;
+  c.rq = c.pq ? blockIdx.x % q.nrings : 0u;
+  c.wq = c.rq;
   c.stg = smem;
   c.l1 = smem + 64;
   c.far = c.l1 + l1_cap_alloc;
@@ -1145,7 +1468,8 @@ __device__ __forceinline__ QueryDesc load_desc_coherent(const QueryDesc* d) {
 // per SIMD are asked of the register allocator: the worker runs up to 12
 // workgroups per CU (batches and the server fill the device), and the limit
 // also measured faster at the default launch sizes.
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) mlmq_worker(LaunchArgs a) {
+template <bool kPQ>
+__device__ __forceinline__ void worker_body(const LaunchArgs& a) {
   extern __shared__ uint64_t smem[];
   const uint64_t t0 = (uint64_t)wall_clock64();
   uint32_t* const my_beat = a.beats ? a.beats + blockIdx.x : nullptr;
@@ -1155,18 +1479,27 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) ml
     if (qi == kInf) break;
     Ctx c;
     setup_ctx(c, a.queries[qi], smem, a.l1_cap, a.l1_two, a.stage, &a.batch->cancel.v, t0 + a.timeout_ticks,
-              a.cap_wait_ticks, my_beat);
+              a.cap_wait_ticks, my_beat, kPQ);
     run_query(c);
     flush_counters(c);
     if (lane() == 0) add32(&c.q.ctrl->finished.v, 1u);
   }
 }
 
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) mlmq_worker(LaunchArgs a) {
+  worker_body<false>(a);
+}
+// The same worker with the L2 priority-queue code compiled in.
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) mlmq_worker_pq(LaunchArgs a) {
+  worker_body<true>(a);
+}
+
 // Resident server kernel: each wave repeatedly joins the oldest open slot,
 // works on that query until it terminates, and leaves. Idle waves sleep and
 // leave the kernel on the host's stop flag or after idle_exit_ticks without
 // work (the host relaunches the kernel when work arrives and none is left).
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) mlmq_server_worker(ServerArgs a) {
+template <bool kPQ>
+__device__ __forceinline__ void server_body(const ServerArgs& a) {
   extern __shared__ uint64_t smem[];
   uint64_t last_busy = (uint64_t)wall_clock64();
   uint32_t idle = 0;
@@ -1194,7 +1527,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) ml
       const QueryDesc q = load_desc_coherent(a.slots + s);
       Ctx c;
       setup_ctx(c, q, smem, a.l1_cap, a.l1_two, a.stage, &a.ctl->cancel.v, (uint64_t)wall_clock64() + a.timeout_ticks,
-                a.cap_wait_ticks, nullptr);
+                a.cap_wait_ticks, nullptr, kPQ);
       run_query(c);
       flush_counters(c);
       if (l == 0) {
@@ -1232,28 +1565,40 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) ml
   }
 }
 
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) mlmq_server_worker(ServerArgs a) {
+  server_body<false>(a);
+}
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) mlmq_server_worker_pq(ServerArgs a) {
+  server_body<true>(a);
+}
+
 // Per-query reset: dist = UINT32_MAX except dist[source] = 0, all L2 slots
 // free except ring 0 / slot 0, which holds the source (it is written through
 // to L2 before the worker starts, Section 4.1), counters zero, reservation 1.
+// With priority queues every node is empty and unlocked, every heap has no
+// node, and queue 0's partial buffer holds the source (pq_in = 1).
 __device__ __forceinline__ void init_query(const QueryDesc& q, uint32_t tid, uint32_t stride) {
   const uint32_t n = q.n, src = q.source;
+  const bool pq = q.l2_type == MLMQ_L2_PQ;
   uint32_t* dist = q.dist;
   for (uint32_t i = tid; i < n; i += stride) dist[i] = i == src ? 0u : kInf;
   const uint32_t nh = q.nrings << q.nb_log2;
   uint64_t* hdr = q.hdr;
-  for (uint32_t i = tid; i < nh; i += stride) hdr[i] = i == 0 ? ((1ull << 32) | 1ull) : 0ull;
+  const uint64_t first = pq ? (1ull << 32) : ((1ull << 32) | 1ull);
+  for (uint32_t i = tid; i < nh; i += stride) hdr[i] = i == 0 ? first : 0ull;
   const uint32_t hc = q.hub_cap;
   for (uint32_t i = tid; i < hc; i += stride) {
     q.hub_cur[i] = 0;
     q.hub_pub[i] = 0;
   }
   for (uint32_t i = tid; i < q.nrings; i += stride) {
-    q.rings[i].tail.v = i == 0 ? 1u : 0u;
+    q.rings[i].tail.v = (i == 0 && !pq) ? 1u : 0u;
     q.rings[i].head.v = 0;
   }
   const uint32_t cw = sizeof(QueryCtrl) / 4;
   uint32_t* cwp = reinterpret_cast<uint32_t*>(q.ctrl);
-  for (uint32_t i = tid; i < cw; i += stride) cwp[i] = 0;
+  const uint32_t* pq_in = &q.ctrl->pq_in.v;
+  for (uint32_t i = tid; i < cw; i += stride) cwp[i] = (pq && cwp + i == pq_in) ? 1u : 0u;
   if (tid == 0) q.data[0] = make_elem(src, 0);
 }
 
@@ -1399,6 +1744,57 @@ __global__ void __launch_bounds__(256) mlmq_check_vertices(const uint32_t* dist,
   if (lane() == 0 && nbad) atomicAdd(bad, (unsigned long long)nbad);
 }
 
+// ------------------------------------------------------------ latency probes
+
+// Dependent-hop chain: lane 0 of one wave walks `hops` hops from v0; each hop
+// loads the row bounds of the current vertex, then one of its edge words
+// (picked by the hop number), then takes an agent-scope atomicMin on the
+// neighbour's label, and the next vertex depends on the value the atomic
+// returned -- the three memory operations of one relaxation, each waiting for
+// the one before, with no queue in between. out[0] = wall-clock ticks.
+__global__ void __launch_bounds__(64) mlmq_hop_probe(const int32_t* off, const uint64_t* adj, uint32_t* lab,
+                                                    uint32_t n, uint32_t v0, uint32_t hops, uint64_t* out) {
+  if (threadIdx.x != 0) return;
+  uint32_t v = v0;
+  const uint64_t t0 = (uint64_t)wall_clock64();
+  for (uint32_t i = 0; i < hops; ++i) {
+    const int32_t b = off[v], e = off[v + 1];
+    if (e <= b) {
+      v = v0;
+      continue;
+    }
+    const uint64_t a = adj[(uint32_t)b + i % (uint32_t)(e - b)];
+    const uint32_t u = (uint32_t)a;
+    const uint32_t old = __hip_atomic_fetch_min(lab + u, i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    v = u + (old == 0xFFFFFFFEu ? 1u : 0u);  // never taken, but waits for the atomic
+    if (v >= n) v = v0;
+  }
+  out[0] = (uint64_t)wall_clock64() - t0;
+}
+
+// Hand-off between two workgroups (placed on different XCDs by the round-robin
+// dispatch): they take turns incrementing one agent-scope word, each waiting
+// to see the other's value -- the round trip of publishing work that another
+// wave picks up. Every wait gives up at the deadline (out[1] = 1 then).
+// out[0] = ticks for `rounds` round trips, measured by workgroup 0.
+__global__ void __launch_bounds__(64) mlmq_handoff_probe(uint32_t* word, uint32_t rounds, uint64_t limit_ticks,
+                                                        uint64_t* out) {
+  if (threadIdx.x != 0 || blockIdx.x > 1) return;
+  const uint32_t me = blockIdx.x;
+  const uint64_t t0 = (uint64_t)wall_clock64();
+  for (uint32_t r = 0; r < rounds; ++r) {
+    const uint32_t want = 2u * r + me;  // workgroup 0 moves on even values, 1 on odd ones
+    while (__hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != want) {
+      if ((uint64_t)wall_clock64() - t0 > limit_ticks) {
+        if (me == 0) out[1] = 1;
+        return;
+      }
+    }
+    __hip_atomic_store(word, want + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  if (me == 0) out[0] = (uint64_t)wall_clock64() - t0;
+}
+
 // ------------------------------------------------------------ host launchers
 
 size_t worker_lds_bytes(uint32_t waves, uint32_t l1_cap, bool two_rings, bool stage) {
@@ -1414,7 +1810,10 @@ hipError_t launch_init(const QueryDesc* d_queries, BatchCtrl* d_batch, int nq, u
 }
 
 hipError_t launch_worker(const LaunchArgs& a, uint32_t grid, uint32_t wg_size, size_t lds, hipStream_t s) {
-  hipLaunchKernelGGL(mlmq_worker, dim3(grid), dim3(wg_size), lds, s, a);
+  if (a.pq)
+    hipLaunchKernelGGL(mlmq_worker_pq, dim3(grid), dim3(wg_size), lds, s, a);
+  else
+    hipLaunchKernelGGL(mlmq_worker, dim3(grid), dim3(wg_size), lds, s, a);
   return hipGetLastError();
 }
 
@@ -1431,7 +1830,10 @@ hipError_t launch_gather(const QueryDesc* d_queries, int nq, QueryResult* d_out,
 }
 
 hipError_t launch_server_worker(const ServerArgs& a, uint32_t grid, size_t lds, hipStream_t s) {
-  hipLaunchKernelGGL(mlmq_server_worker, dim3(grid), dim3(64), lds, s, a);
+  if (a.pq)
+    hipLaunchKernelGGL(mlmq_server_worker_pq, dim3(grid), dim3(64), lds, s, a);
+  else
+    hipLaunchKernelGGL(mlmq_server_worker, dim3(grid), dim3(64), lds, s, a);
   return hipGetLastError();
 }
 
@@ -1469,12 +1871,24 @@ hipError_t launch_check(const int32_t* off, const uint64_t* adj, const uint32_t*
   return hipGetLastError();
 }
 
-hipError_t server_occupancy(size_t lds, int* wgs_per_cu) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(wgs_per_cu, mlmq_server_worker, 64, lds);
+hipError_t launch_latency_probes(const int32_t* off, const uint64_t* adj, uint32_t* lab, uint32_t n, uint32_t v0,
+                                 uint32_t hops, uint32_t* word, uint32_t rounds, uint64_t limit_ticks, uint64_t* out,
+                                 hipStream_t s) {
+  hipLaunchKernelGGL(mlmq_hop_probe, dim3(1), dim3(64), 0, s, off, adj, lab, n, v0, hops, out);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(mlmq_handoff_probe, dim3(2), dim3(64), 0, s, word, rounds, limit_ticks, out + 2);
+  return hipGetLastError();
 }
 
-hipError_t worker_occupancy(uint32_t wg_size, size_t lds, int* wgs_per_cu) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(wgs_per_cu, mlmq_worker, (int)wg_size, lds);
+hipError_t server_occupancy(size_t lds, bool pq, int* wgs_per_cu) {
+  return pq ? hipOccupancyMaxActiveBlocksPerMultiprocessor(wgs_per_cu, mlmq_server_worker_pq, 64, lds)
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(wgs_per_cu, mlmq_server_worker, 64, lds);
+}
+
+hipError_t worker_occupancy(uint32_t wg_size, size_t lds, bool pq, int* wgs_per_cu) {
+  return pq ? hipOccupancyMaxActiveBlocksPerMultiprocessor(wgs_per_cu, mlmq_worker_pq, (int)wg_size, lds)
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(wgs_per_cu, mlmq_worker, (int)wg_size, lds);
 }
 
 // ------------------------------------------------------------ allocation-free solve

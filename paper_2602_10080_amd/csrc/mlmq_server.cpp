@@ -382,7 +382,7 @@ int mlmq_server_create(const mlmq_graph* const* graphs, int32_t ngraphs, uint64_
   s->nslots = max_slots;
   s->budget = mem_budget_bytes;
   uint32_t l1_alloc = 64;
-  bool two = false, stage = false;
+  bool two = false, stage = false, pq = false;
   uint32_t timeout_ms = 0;
   for (int32_t i = 0; i < ngraphs; ++i) {
     mlmq_config tmp;
@@ -395,6 +395,7 @@ int mlmq_server_create(const mlmq_graph* const* graphs, int32_t ngraphs, uint64_
     if (cc.l1_type != MLMQ_L1_NONE) l1_alloc = std::max(l1_alloc, cc.l1_cap);
     two |= cc.l1_type == MLMQ_L1_NEARFAR;
     stage |= cc.l2_type == MLMQ_L2_BUCKET;
+    pq |= cc.l2_type == MLMQ_L2_PQ;
     timeout_ms = std::max(timeout_ms, cc.timeout_ms);
   }
   auto fail = [&](int code) {
@@ -405,7 +406,7 @@ int mlmq_server_create(const mlmq_graph* const* graphs, int32_t ngraphs, uint64_
   s->lds = worker_lds_bytes(1, l1_alloc, two, stage);
   if (s->lds > di->lds_per_wg) return fail(set_error(MLMQ_ERR_INVALID_ARG, "L1 does not fit in LDS"));
   int per_cu = 0;
-  hipError_t e = server_occupancy(s->lds, &per_cu);
+  hipError_t e = server_occupancy(s->lds, pq, &per_cu);
   if (e != hipSuccess) return fail(hip_fail(e, "occupancy query"));
   if (per_cu < 1) return fail(set_error(MLMQ_ERR_INVALID_ARG, "server kernel does not fit on a CU"));
   // One workgroup per CU fewer than fit: the admission kernels (query init,
@@ -463,6 +464,7 @@ int mlmq_server_create(const mlmq_graph* const* graphs, int32_t ngraphs, uint64_
   a.l1_cap = l1_alloc;
   a.l1_two = two ? 1u : 0u;
   a.stage = stage ? 1u : 0u;
+  a.pq = pq ? 1u : 0u;
   s->timeout_ms = timeout_ms ? timeout_ms : 60000;
   a.timeout_ticks = (uint64_t)s->timeout_ms * di->ticks_per_ms;
   a.cap_wait_ticks = 20ull * di->ticks_per_ms;

@@ -1,0 +1,153 @@
+#!/usr/bin/env python3
+"""Timing corpus for the learned configuration selector (Section 3.5).
+
+Runs every candidate template of the library (and the feature-driven default)
+on a seeded synthetic corpus of graphs shaped like the paper's graph classes:
+road-like and mesh-like grids, power-law RMAT graphs and uniform random
+graphs, at several sizes, degree skews and weight ranges. For each graph and
+each of two sources it records the device time of the solve (init +
+persistent kernel). Every template's distance vector is compared with the
+default's, which the library's device optimality check accepts first, so the
+run is also a sweep of the configuration space for identical results.
+
+Usage (on a GPU): python -m paper_2602_10080_amd.selector.collect OUT.csv
+Writes one CSV row per (graph, source, template).
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import graphgen as gg  # noqa: E402
+
+FEATURES = ("n", "nnz", "avg_deg", "max_deg", "std_deg", "avg_w", "std_w", "max_w")
+
+
+def corpus():
+    """(name, builder) pairs; seeds are fixed, so the corpus is reproducible.
+    Every third graph or so goes to the held-out split (graph index mod 10 in
+    {2, 5, 8})."""
+    out = []
+    seed = 100
+    for (r, c) in ((128, 128), (256, 256), (128, 1024), (512, 512), (1024, 1024)):
+        for p in (0.0, 0.05, 0.2):
+            for wmax in (255, 16):
+                seed += 1
+                out.append((f"grid{r}x{c}-p{p}-w{wmax}",
+                            (lambda r=r, c=c, p=p, wmax=wmax, s=seed: gg.grid(r, c, p, wmax=wmax, seed=s))))
+    for (r, c) in ((2048, 2048), (1536, 1536)):
+        seed += 1
+        out.append((f"grid{r}x{c}-p0.05-w255", (lambda r=r, c=c, s=seed: gg.grid(r, c, 0.05, seed=s))))
+    for scale in (14, 16, 18, 20):
+        for ef in (4, 16):
+            for (a, b) in ((0.57, 0.19), (0.45, 0.22)):
+                for wmax in (255, 65535):
+                    seed += 1
+                    cc = b
+                    out.append((f"rmat{scale}-ef{ef}-a{a}-w{wmax}",
+                                (lambda scale=scale, ef=ef, a=a, b=b, cc=cc, wmax=wmax, s=seed:
+                                 gg.rmat(scale, ef, a, b, cc, wmax=wmax, seed=s))))
+    for scale in (21, 22):
+        seed += 1
+        out.append((f"rmat{scale}-ef16-a0.57-w255", (lambda scale=scale, s=seed: gg.rmat(scale, 16, seed=s))))
+    for lg in (14, 16, 18, 20):
+        for deg in (4, 16):
+            for wmax in (255, 65535):
+                seed += 1
+                out.append((f"uniform{lg}-d{deg}-w{wmax}",
+                            (lambda lg=lg, deg=deg, wmax=wmax, s=seed:
+                             gg.uniform(1 << lg, deg << lg, wmax=wmax, seed=s))))
+    return out
+
+
+def split_of(i: int) -> str:
+    return "test" if i % 10 in (2, 5, 8) else "train"
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("out")
+    ap.add_argument("--only", default="", help="comma-separated graph indices (default: all)")
+    ap.add_argument("--reps", type=int, default=1, help="timed runs per (source, template); the minimum is kept")
+    args = ap.parse_args()
+
+    import torch
+    import paper_2602_10080_amd as mlmq
+    assert torch.cuda.is_available(), "needs a GPU"
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    K = mlmq.candidate_count()
+    graphs = corpus()
+    pick = [int(x) for x in args.only.split(",") if x] or list(range(len(graphs)))
+    fields = ["graph", "name", "split", *FEATURES, "source", "template", "status", "kernel_ms", "worker_ms",
+              "edges", "expansions", "equal"]
+    t_all = time.perf_counter()
+    mismatches = 0
+    with open(args.out, "w", newline="") as fh:
+        wr = csv.writer(fh)
+        wr.writerow(fields)
+        for gi in pick:
+            name, make = graphs[gi]
+            t0 = time.perf_counter()
+            csr = make()
+            f = mlmq.features(csr)
+            g = mlmq.Graph.from_csr(csr)
+            srcs = [gg.max_degree_vertex(csr), int(gg.sample_sources(csr, 1, seed=gi)[0])]
+            ref = []
+            base_ms = []
+            for s in srcs:
+                out = mlmq.new_dist(csr.n)
+                _, st = mlmq.sssp(g, s, out=out, config=mlmq.candidate_config(g, -1), stream=stream, stats=True)
+                bad, _ = mlmq.check(g, s, out, stream=stream)
+                if bad:
+                    raise SystemExit(f"{name}: the default config's vector fails the device check ({bad})")
+                ref.append(out)
+                base_ms.append(st["kernel_ms"])
+            rows = 0
+            for t in range(-1, K):
+                cfg = mlmq.candidate_config(g, t)
+                # a candidate may take at most 8x the default's time (+20 ms)
+                cfg.timeout_ms = int(8 * max(base_ms) + 20)
+                cfg.max_retries = 2
+                for si, s in enumerate(srcs):
+                    out = mlmq.new_dist(csr.n)
+                    best, status, st = None, 0, {}
+                    for _ in range(args.reps):
+                        try:
+                            _, st = mlmq.sssp(g, s, out=out, config=cfg, stream=stream, stats=True)
+                            ms = st["kernel_ms"]
+                            best = ms if best is None else min(best, ms)
+                        except mlmq.MlmqError as e:
+                            status = e.code
+                            break
+                    eq = bool(torch.equal(out, ref[si])) if status == 0 else None
+                    if status == 0 and not eq:
+                        mismatches += 1
+                        print(f"MISMATCH {name} source {s} template {t}", flush=True)
+                    wr.writerow([gi, name, split_of(gi), *[f"{f[k]:.9g}" for k in FEATURES], si, t, status,
+                                 f"{best:.5f}" if best is not None else "", f"{st.get('worker_ms', 0):.5f}",
+                                 st.get("edges", 0), st.get("expansions", 0), int(bool(eq))])
+                    rows += 1
+            fh.flush()
+            g.close()
+            del ref
+            torch.cuda.empty_cache()
+            print(f"[collect] {gi} {name}: n={csr.n} m={csr.m} default {base_ms[0]:.2f}/{base_ms[1]:.2f} ms, "
+                  f"{rows} rows in {time.perf_counter() - t0:.1f}s (total {time.perf_counter() - t_all:.0f}s)",
+                  flush=True)
+    print(f"[collect] done: {len(pick)} graphs, {mismatches} mismatching vectors", flush=True)
+    if mismatches:
+        sys.exit(1)
+
+
+if __name__ == "__main__":
+    main()

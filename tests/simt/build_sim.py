@@ -47,17 +47,23 @@ def transformed_source(checked: bool = False) -> str:
 
 
 def build(out_dir: str, sanitize: bool = False, checked: bool = True) -> str:
-    os.makedirs(out_dir, exist_ok=True)
-    inc = os.path.join(out_dir, "sim_kernels.inc")
-    with open(inc, "w") as f:
+    """Builds into a directory of this process's own, then moves the library
+    into place (parallel test workers may build at the same time)."""
+    work = os.path.join(out_dir, "tmp%d" % os.getpid())
+    os.makedirs(work, exist_ok=True)
+    with open(os.path.join(work, "sim_kernels.inc"), "w") as f:
         f.write(transformed_source(checked))
     lib = os.path.join(out_dir, "libsim%s.so" % ("_asan" if sanitize else ""))
+    tmp = os.path.join(work, os.path.basename(lib))
     cmd = ["g++", "-std=c++20", "-O1", "-g", "-fPIC", "-shared", "-pthread", "-w",
-           "-I", HERE, "-iquote", CSRC, "-iquote", out_dir,
-           os.path.join(HERE, "harness.cpp"), "-o", lib]
+           "-I", HERE, "-iquote", CSRC, "-iquote", work,
+           os.path.join(HERE, "harness.cpp"), "-o", tmp]
     if sanitize:
         cmd[1:1] = ["-fsanitize=address,undefined", "-fno-omit-frame-pointer"]
     subprocess.check_call(cmd)
+    os.replace(tmp, lib)
+    os.remove(os.path.join(work, "sim_kernels.inc"))
+    os.rmdir(work)
     return lib
 
 

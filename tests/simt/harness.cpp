@@ -51,7 +51,7 @@ extern "C" int sim_sssp(int32_t n, const int32_t* off, const int32_t* col, const
   const int64_t m = off[n];
   std::vector<uint64_t> adj((size_t)m + 1);
   for (int64_t e = 0; e < m; ++e) adj[e] = (uint32_t)col[e] | ((uint64_t)w[e] << 32);
-  const uint32_t nrings = k[2] == 1 ? k[7] : 1;
+  const uint32_t nrings = k[2] == 1 ? k[7] : (k[2] == 2 ? k[17] : 1);
   const uint32_t nb_log2 = k[12], hub_cap = k[13];
   const uint64_t nh = (uint64_t)nrings << nb_log2;
   QueryCtrl* ctrl = zalloc<QueryCtrl>(1);
@@ -145,7 +145,10 @@ extern "C" int sim_sssp(int32_t n, const int32_t* off, const int32_t* col, const
         simt::bidx = dim3(g);
         simt::bdim = dim3(wg_size);
         simt::gdim = dim3(nwg);
-        mlmq_worker(a);
+        if (k[2] == MLMQ_L2_PQ)
+          mlmq_worker_pq(a);
+        else
+          mlmq_worker(a);
       });
   for (auto& t : th) t.join();
   if (getenv("SIM_DUMP")) {
@@ -250,7 +253,7 @@ extern "C" int sim_l1_example(uint32_t l1_type, uint32_t delta1, uint32_t* read_
     simt::group->lds = lds;
     Ctx c;
     setup_ctx(c, *q, reinterpret_cast<uint64_t*>(lds), cap, two ? 1u : 0u, 0u, &cancel, ~0ull >> 1, 1000000ull,
-              nullptr);
+              nullptr, false);
     const uint32_t ds[3] = {5, 1, 2};
     for (uint32_t i = 0; i < 3; ++i) write_l1(c, make_elem(i, ds[i]), lane() == 0);
     uint64_t e = 0;
@@ -308,7 +311,7 @@ extern "C" int sim_server(int32_t n, const int32_t* off, const int32_t* col, con
   const int64_t m = off[n];
   std::vector<uint64_t> adj((size_t)m + 1);
   for (int64_t e = 0; e < m; ++e) adj[e] = (uint32_t)col[e] | ((uint64_t)w[e] << 32);
-  const uint32_t nrings = k[2] == 1 ? k[7] : 1;
+  const uint32_t nrings = k[2] == 1 ? k[7] : (k[2] == 2 ? k[17] : 1);
   const uint32_t nb_log2 = k[12], hub_cap = k[13];
   const uint64_t nh = (uint64_t)nrings << nb_log2;
   QueryDesc* slots = zalloc<QueryDesc>(64);
@@ -362,7 +365,10 @@ extern "C" int sim_server(int32_t n, const int32_t* off, const int32_t* col, con
         simt::bidx = dim3(g);
         simt::bdim = dim3(64);
         simt::gdim = dim3(nwg);
-        mlmq_server_worker(a);
+        if (k[2] == MLMQ_L2_PQ)
+          mlmq_server_worker_pq(a);
+        else
+          mlmq_server_worker(a);
       });
 
   struct Mem {
@@ -456,4 +462,117 @@ extern "C" int sim_server(int32_t n, const int32_t* off, const int32_t* col, con
   free(done);
   free(ctl);
   return finished == nq ? 0 : -1;
+}
+
+// Priority queues alone (Section 4.2, L2PQ / L2MPQ): nwaves one-wave
+// workgroups each write `rounds` batches of 1..64 random elements (element
+// ids unique: wave << 20 | round << 6 | lane) into pnum queues, taking one
+// batch after every `pop_every` writes; afterwards one wave takes everything
+// left. Every element written lands in ins[] and every element taken in
+// out[] (counts in *nin, *nout); *unsorted counts taken batches that are not
+// ascending, and with a single wave and pop_every = 0, *disorder counts
+// taken elements smaller than one taken before (an exact priority queue
+// gives 0). status: [device status, pq_in, elements still queued].
+extern "C" int sim_pq(uint32_t nwaves, uint32_t pnum, uint32_t nb_log2, uint32_t rounds, uint32_t pop_every,
+                      uint32_t dmax, uint64_t seed, uint64_t* ins, uint32_t* nin, uint64_t* out, uint32_t* nout,
+                      uint32_t* unsorted, uint32_t* disorder, uint32_t* status) {
+  const uint64_t nh = (uint64_t)pnum << nb_log2;
+  QueryCtrl* ctrl = zalloc<QueryCtrl>(1);
+  RingCtr* rings = zalloc<RingCtr>(pnum);
+  uint64_t* hdr = zalloc<uint64_t>(nh);
+  uint64_t* data = zalloc<uint64_t>(nh * 64);
+  // what the init kernel leaves for priority queues with no source element
+  std::memset(ctrl, 0, sizeof(QueryCtrl));
+  std::memset(rings, 0, sizeof(RingCtr) * pnum);
+  std::memset(hdr, 0, sizeof(uint64_t) * nh);
+  QueryDesc* q = zalloc<QueryDesc>(1);
+  std::memset(q, 0, sizeof(QueryDesc));
+  q->ctrl = ctrl;
+  q->rings = rings;
+  q->hdr = hdr;
+  q->data = data;
+  q->n = 1u << 30;
+  q->nb_log2 = nb_log2;
+  q->nrings = pnum;
+  q->hub_cap = 1;
+  q->l1_type = MLMQ_L1_NONE;
+  q->l2_type = MLMQ_L2_PQ;
+  q->l1_cap = 64;
+  q->bnum = 1;
+  q->th_v = 32;
+  q->want_wgs = nwaves;
+  uint32_t cancel = 0;
+  std::atomic<uint32_t> ni{0}, no{0}, bad_batches{0};
+  const uint64_t limit = 60ull * 1000 * 100000ull;  // 60 s of wall-clock ticks
+  auto take = [&](Ctx& c, uint32_t& last_d, bool track) {
+    uint64_t e = 0;
+    bool ok = false;
+    const bool got = pq_read(c, e, ok);
+    if (!got) return false;
+    // ascending within the batch: each taken lane is >= the previous lane
+    const uint64_t prev = shfl64(e, lane() ? lane() - 1u : 0u);
+    const bool okp = __shfl((int)ok, lane() ? (int)lane() - 1 : 0) != 0;
+    if (ballot(ok && lane() > 0 && okp && e < prev)) bad_batches++;
+    const uint64_t m = ballot(ok);
+    uint32_t base = 0;
+    if (lane() == 0) base = no.fetch_add(popc(m));
+    base = lane_val(base, 0);
+    if (ok) out[base + rank_of(m)] = e;
+    if (track) {
+      // the batch is ascending (checked above): compare its first element
+      // with the last one taken before, then remember its last
+      const uint32_t k = popc(m);
+      const uint32_t first = lane_val(elem_d(e), 0), lastb = lane_val(elem_d(e), k - 1u);
+      if (lane() == 0 && first < last_d) (*disorder)++;
+      last_d = lastb;
+    }
+    return true;
+  };
+  *disorder = 0;
+  run_grid(nwaves, 64, [&] {
+    Ctx c;
+    setup_ctx(c, *q, nullptr, 64, 0u, 0u, &cancel, (uint64_t)wall_clock64() + limit, 1000000ull, nullptr, true);
+    uint64_t x = seed ^ (0x9E3779B97F4A7C15ull * (blockIdx.x + 1u));
+    uint32_t last_d = 0;
+    for (uint32_t r = 0; r < rounds && !c.stop; ++r) {
+      x = x * 6364136223846793005ull + 1442695040888963407ull;
+      const uint32_t k = 1u + (uint32_t)((x >> 33) % 64u);
+      uint64_t y = x ^ (0xD1B54A32D192ED03ull * (lane() + 1u));
+      y ^= y >> 29;
+      y *= 0xBF58476D1CE4E5B9ull;
+      y ^= y >> 32;
+      const bool ok = lane() < k;
+      const uint64_t e = make_elem((blockIdx.x << 20) | (r << 6) | lane(), (uint32_t)(y % dmax));
+      const uint64_t m = ballot(ok);
+      uint32_t base = 0;
+      if (lane() == 0) base = ni.fetch_add(popc(m));
+      base = lane_val(base, 0);
+      if (ok) ins[base + rank_of(m)] = e;
+      pq_write(c, e, ok);
+      if (pop_every && (r % pop_every) == pop_every - 1u) take(c, last_d, false);
+    }
+    if (c.stop && lane() == 0) status[0] = ctrl->error.v;
+  });
+  run_grid(1, 64, [&] {
+    Ctx c;
+    setup_ctx(c, *q, nullptr, 64, 0u, 0u, &cancel, (uint64_t)wall_clock64() + limit, 1000000ull, nullptr, true);
+    uint32_t last_d = 0;
+    const bool track = nwaves == 1 && pop_every == 0;
+    while (!c.stop && take(c, last_d, track)) {
+    }
+  });
+  status[0] = ctrl->error.v;
+  status[1] = ctrl->pq_in.v;
+  uint32_t left = 0;
+  for (uint32_t i = 0; i < pnum; ++i) left += rings[i].tail.v * 64u + (uint32_t)(hdr[(uint64_t)i << nb_log2] >> 32);
+  status[2] = left;
+  *nin = ni.load();
+  *nout = no.load();
+  *unsorted = bad_batches.load();
+  free(ctrl);
+  free(rings);
+  free(hdr);
+  free(data);
+  free(q);
+  return 0;
 }

@@ -155,6 +155,7 @@ inline uint32_t __builtin_amdgcn_mbcnt_hi(uint32_t m, uint32_t acc) {
 inline int __popcll(unsigned long long m) { return __builtin_popcountll(m); }
 inline int __ffsll(long long m) { return __builtin_ffsll(m); }
 inline int __clzll(long long m) { return m ? __builtin_clzll((unsigned long long)m) : 64; }
+inline int __clz(int x) { return x ? __builtin_clz((unsigned)x) : 32; }
 inline unsigned long long atomicAdd(unsigned long long* p, unsigned long long v) {
   return __atomic_fetch_add(p, v, __ATOMIC_SEQ_CST);
 }

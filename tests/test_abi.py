@@ -4,6 +4,7 @@ argument checks) behaves; device calls on a GPU-less host fail cleanly."""
 import ctypes
 import os
 import re
+import subprocess
 
 import numpy as np
 import pytest
@@ -34,11 +35,17 @@ def test_library_exports_every_declared_symbol():
     assert set(names) == set(mlmq.EXPORTS)
 
 
-def test_struct_sizes_match_header():
+def test_struct_sizes_match_header(tmp_path):
+    """The binding's structures have the sizes a C compiler gives the
+    header's (the library rejects a config whose struct_size differs)."""
     mlmq = _mlmq()
-    assert ctypes.sizeof(mlmq.Config) == 88
-    assert ctypes.sizeof(mlmq.Stats) == 144
-    assert ctypes.sizeof(mlmq.Features) == 64
+    src = tmp_path / "sizes.c"
+    src.write_text('#include <stdio.h>\n#include "mlmq.h"\nint main(void) { printf("%zu %zu %zu", '
+                   'sizeof(mlmq_config), sizeof(mlmq_stats), sizeof(mlmq_features)); return 0; }\n')
+    exe = tmp_path / "sizes"
+    subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    sizes = [int(x) for x in subprocess.check_output([str(exe)]).split()]
+    assert sizes == [ctypes.sizeof(mlmq.Config), ctypes.sizeof(mlmq.Stats), ctypes.sizeof(mlmq.Features)]
 
 
 def test_config_default_and_struct_size_check():

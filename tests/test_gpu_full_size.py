@@ -114,6 +114,30 @@ def test_bucket_l2_full_size(name, cfg_name):
     assert st["status"] == 0
 
 
+# Section 5's priority-queue case study on a road-sized graph (the paper uses
+# the 264k-vertex NY road network; the 512x512 road-like grid stands in) and
+# on a power-law graph: the priority queue alone, under L0 + L1, and as a
+# multi-queue.
+PQ_CONFIGS = {
+    "L2PQ": dict(l0_rows=0, l1_type=0, l2_type=2, pnum=1, th_hub=0),
+    "L0-L1NF-L2PQ": dict(l0_rows=1, l1_type=2, l2_type=2, pnum=1, delta1=128, th_hub=0),
+    "L2MPQ16": dict(l0_rows=0, l1_type=0, l2_type=2, pnum=16, th_hub=0),
+    "L0-L1NF-L2MPQ16": dict(l0_rows=1, l1_type=2, l2_type=2, pnum=16, delta1=128, th_hub=0),
+}
+
+
+@pytest.mark.parametrize("cfg_name", list(PQ_CONFIGS))
+@pytest.mark.parametrize("name", ["road512", "rmat20"])
+def test_priority_queues_case_study_graphs(name, cfg_name):
+    csr, src = (gg.grid(512, 512, 0.05, seed=11), 256 * 512 + 256) if name == "road512" else \
+        (lambda g: (g, gg.max_degree_vertex(g)))(gg.rmat(20, 16, seed=13))
+    key = "pq-" + name
+    if key not in _CACHE:
+        _CACHE[key] = oracle.dijkstra(csr, src)
+    st = _solve_and_check(f"{name}/{cfg_name}", csr, src, _CACHE[key], dict(PQ_CONFIGS[cfg_name], timeout_ms=20000))
+    assert st["status"] == 0
+
+
 def test_uniform_4m_wide_weights_sampled_sources():
     """The serving workload's overflow-unsafe graph (weights up to 65535)."""
     csr = gg.uniform(1 << 22, 1 << 25, wmax=65535, seed=15)

@@ -49,6 +49,12 @@ CONFIGS = {
     "L0off-L1NF-L2V-atomic": dict(l0_rows=0, l1_type=2, l2_type=0, relax_mode=1, delta1=64, th_hub=0),
     "L0x1-L1FQ-L2DQ-atomic": dict(l0_rows=1, l1_type=3, l2_type=1, relax_mode=1, bmax=16, bnum=1, delta2_log2=6,
                                   delta1=64, th_hub=0),
+    # L2 priority queue alone and under L0/L1, and the multi-queue (Section 4.2)
+    "L0off-L1none-L2PQ": dict(l0_rows=0, l1_type=0, l2_type=2, pnum=1, th_hub=0),
+    "L0x1-L1NF-L2PQ": dict(l0_rows=1, l1_type=2, l2_type=2, pnum=1, delta1=64, th_hub=0),
+    "L0x1-L1V-L2MPQ8-hub64": dict(l0_rows=1, l1_type=1, l2_type=2, pnum=8, th_v=8, th_hub=64, hub_chunk=64),
+    "L0x2-L1SLF-L2MPQ32": dict(l0_rows=2, l1_type=4, l2_type=2, pnum=32, l1_cap=128, th_hub=0),
+    "tinyL2-PQ": dict(l0_rows=0, l1_type=0, l2_type=2, pnum=2, l2_capacity=1024, th_hub=0),
 }
 
 
@@ -198,7 +204,8 @@ def test_batch_matches_alone(dev_graphs, oracle_dist):
         assert torch.equal(o1, o2)
 
 
-@pytest.mark.parametrize("cfg_name", [None, "L0x2-L1V-L2V", "L0x1-L1NF-L2DQ", "L0x1-L1SLF-L2V", "L0off-L1NF-L2V-atomic"])
+@pytest.mark.parametrize("cfg_name", [None, "L0x2-L1V-L2V", "L0x1-L1NF-L2DQ", "L0x1-L1SLF-L2V", "L0off-L1NF-L2V-atomic",
+                                      "L0x1-L1NF-L2PQ"])
 @pytest.mark.parametrize("graph_name", ["grid64", "road96x80", "rmat12", "uniform", "path", "star", "isolated_src",
                                         "multi"])
 def test_bfs_parity(dev_graphs, graph_name, cfg_name):

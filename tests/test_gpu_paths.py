@@ -2,9 +2,11 @@
 test's false alarm (a saturating candidate that is not a shortest path) in
 the plain, batched and serving forms; the device watchdog; the refusal of
 multi-wave workgroups; batches whose queue layout changes between launches;
-concurrent solves from two host threads on two streams; and a server whose
-graphs are all power-law (register-bound residency). Every result is compared
-with the oracle element by element (integer arithmetic, tolerance 0)."""
+concurrent solves from two host threads on two streams; a server whose
+graphs are all power-law (register-bound residency); and batches and servers
+that mix priority-queue queries (their own kernel variant) with ring queries.
+Every result is compared with the oracle element by element (integer
+arithmetic, tolerance 0)."""
 import sys
 import threading
 import time
@@ -214,3 +216,54 @@ def test_server_power_law_only_admission_latency():
     for (k, s), o in zip(reqs, outs):
         assert np.array_equal(mlmq.to_numpy(o), oracle.dijkstra(csrs[k], s)), (k, s)
     assert np.percentile(lat, 99) < 100.0, lat.max()
+
+
+def test_priority_queue_queries_in_batch_and_server():
+    """Queries whose L2 is a priority queue (L2PQ) or a multi-queue (L2MPQ)
+    mixed with ring queries in one batched launch and in one server: the
+    library launches the kernel variant that holds the priority-queue code."""
+    mlmq = _mlmq()
+    road = gg.grid(128, 96, 0.05, seed=81)
+    pl = gg.rmat(12, 8, seed=82)
+    gr, gp = mlmq.Graph.from_csr(road), mlmq.Graph.from_csr(pl)
+    pq1 = mlmq.default_config(l0_rows=1, l1_type=2, l2_type=2, pnum=1, delta1=64, th_hub=0)
+    mpq = mlmq.default_config(l0_rows=1, l1_type=1, l2_type=2, pnum=8, th_hub=0)
+    graphs = [gr, gp, gr, gp, gr, gp]
+    csrs = [road, pl, road, pl, road, pl]
+    cfgs = [pq1, mpq, None, None, mpq, pq1]
+    srcs = [0, gg.max_degree_vertex(pl), 64 * 96 + 50, 7, 12287, 100]
+    full = [c if c is not None else g.config() for c, g in zip(cfgs, graphs)]
+    outs, status = mlmq.sssp_batch(graphs, srcs, configs=full)
+    torch.cuda.synchronize()
+    assert status == [0] * 6
+    for c, s, o in zip(csrs, srcs, outs):
+        assert np.array_equal(mlmq.to_numpy(o), oracle.dijkstra(c, s)), s
+    outs = [mlmq.new_dist(c.n) for c in csrs]
+    torch.cuda.synchronize()
+    srv = mlmq.Server([gr, gp], mem_budget_bytes=1 << 28, max_slots=4, config=mpq)
+    try:
+        t = [srv.submit(0 if c is road else 1, s, o) for c, s, o in zip(csrs, srcs, outs)]
+        st = [srv.wait(x, 30000) for x in t]
+    finally:
+        srv.close()
+    assert st == [0] * 6
+    for c, s, o in zip(csrs, srcs, outs):
+        assert np.array_equal(mlmq.to_numpy(o), oracle.dijkstra(c, s)), s
+
+
+def test_latency_probe_runs_and_leaves_graph_intact():
+    """The latency probes (dependent relaxation hops, hand-off between two
+    workgroups) return plausible times, and a solve afterwards is exact (the
+    probe writes only its own scratch labels)."""
+    mlmq = _mlmq()
+    csr = gg.grid(200, 200, 0.05, seed=91)
+    g = mlmq.Graph.from_csr(csr)
+    hop_ns, hand_ns = mlmq.latency_probe(g, 100 * 200 + 100, 4096)
+    _say(f"[probe] hop {hop_ns:.0f} ns, hand-off {hand_ns:.0f} ns")
+    assert 10.0 < hop_ns < 1e5 and 10.0 < hand_ns < 1e5
+    out = mlmq.sssp(g, 5)
+    torch.cuda.synchronize()
+    assert np.array_equal(mlmq.to_numpy(out), oracle.dijkstra(csr, 5))
+    with pytest.raises(mlmq.MlmqError):
+        mlmq.latency_probe(g, csr.n, 16)
+    g.close()

@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 
 # knobs: l0_rows, l1_type, l2_type, l1_cap, l1_wb, delta1, d2_log2, bmax, bnum,
-#        th_v, th_hub, hub_chunk, nb_log2, hub_cap, timeout_ms, relax_mode, unit_w
+#        th_v, th_hub, hub_chunk, nb_log2, hub_cap, timeout_ms, relax_mode, unit_w[, pnum]
 CFG = {
     "L0x2-L1V-L2V": [2, 1, 0, 1024, 64, 256, 7, 32, 4, 32, 0, 2048, 10, 1, 60000, 0, 0],
     "L0off-L1none-L2V": [0, 0, 0, 1024, 64, 256, 7, 32, 4, 32, 0, 2048, 10, 1, 60000, 0, 0],
@@ -31,7 +31,17 @@ CFG = {
     "L0off-L1NF-L2V-atomic": [0, 2, 0, 256, 0, 64, 7, 32, 4, 32, 0, 2048, 10, 1, 60000, 1, 0],
     "L0x1-L1SLF-L2V": [1, 4, 0, 128, 0, 64, 7, 32, 4, 32, 0, 2048, 10, 1, 60000, 0, 0],
     "L0x1-L1SLF-L2DQ-hub": [1, 4, 1, 256, 0, 64, 6, 16, 1, 16, 128, 128, 8, 256, 60000, 0, 0],
+    # priority queues (Section 4.2): alone, under L0 + L1, and as a multi-queue
+    "L1none-L2PQ": [0, 0, 2, 1024, 0, 64, 7, 32, 4, 32, 0, 2048, 8, 1, 60000, 0, 0, 1],
+    "L0x1-L1NF-L2PQ": [1, 2, 2, 256, 0, 64, 7, 32, 4, 32, 0, 2048, 8, 1, 60000, 0, 0, 1],
+    "L0x1-L1V-L2MPQ3-hub": [1, 1, 2, 256, 16, 64, 7, 32, 4, 16, 128, 128, 6, 256, 60000, 0, 0, 3],
 }
+
+
+def _knobs(k):
+    """Knob array with the priority-queue count appended when absent (1)."""
+    k = list(k)
+    return k + [1] * (18 - len(k))
 
 
 @pytest.fixture(scope="module")
@@ -48,7 +58,7 @@ def run(lib, csr, src, knobs, nwg=8):
     col = np.ascontiguousarray(csr.col, np.int32)
     w = np.ascontiguousarray(csr.w, np.uint32)
     dist = np.zeros(csr.n, np.uint32)
-    k = np.array(knobs, np.uint32)
+    k = np.array(_knobs(knobs), np.uint32)
     stats = np.zeros(16, np.uint64)
     status = np.zeros(4, np.uint32)
     vp = ctypes.c_void_p
@@ -88,7 +98,7 @@ def test_kernel_on_cpu_matches_oracle(sim, graph, cfg):
     assert status[2] >= 1
 
 
-@pytest.mark.parametrize("cfg", ["L0x2-L1V-L2V", "L1FQ-L2DQ-hub"])
+@pytest.mark.parametrize("cfg", ["L0x2-L1V-L2V", "L1FQ-L2DQ-hub", "L0x1-L1NF-L2PQ"])
 @pytest.mark.parametrize("nslots,want", [(2, 3), (3, 8)])
 def test_server_kernel_on_cpu_matches_oracle(sim, cfg, nslots, want):
     """Slot protocol of the resident server kernel: queries join, run next to
@@ -102,7 +112,7 @@ def test_server_kernel_on_cpu_matches_oracle(sim, cfg, nslots, want):
     w = np.ascontiguousarray(csr.w, np.uint32)
     dist = np.zeros((nq, csr.n), np.uint32)
     status = np.full(nq, 0xFFFF, np.uint32)
-    k = np.array(CFG[cfg], np.uint32)
+    k = np.array(_knobs(CFG[cfg]), np.uint32)
     vp = ctypes.c_void_p
     sim.sim_server.restype = ctypes.c_int
     rc = sim.sim_server(ctypes.c_int32(csr.n), vp(off.ctypes.data), vp(col.ctypes.data), vp(w.ctypes.data),
@@ -115,7 +125,7 @@ def test_server_kernel_on_cpu_matches_oracle(sim, cfg, nslots, want):
         assert np.array_equal(dist[i], oracle.dijkstra(csr, int(s))), i
 
 
-@pytest.mark.parametrize("cfg", ["L0x2-L1V-L2V", "L1NF-L2DQ", "L0x1-L1SLF-L2V"])
+@pytest.mark.parametrize("cfg", ["L0x2-L1V-L2V", "L1NF-L2DQ", "L0x1-L1SLF-L2V", "L1none-L2PQ"])
 @pytest.mark.parametrize("graph", ["road24", "rmat9"])
 def test_bfs_mode_on_cpu_matches_oracle(sim, graph, cfg):
     """Unit-weight mode (breadth-first levels, Section 5.7)."""
@@ -215,3 +225,52 @@ def test_queue_unit_example(sim, l1_type, delta1, read, left, l2):
     assert list(rd[:nr.value]) == read
     assert list(lf[:nl.value]) == left
     assert list(l2d[:n2.value]) == l2
+
+
+# ------------------------------------------------------------ priority queues alone
+
+def _sim_pq(lib, nwaves, pnum, nb_log2, rounds, pop_every, dmax, seed):
+    cap = nwaves * rounds * 64
+    ins = np.zeros(cap, np.uint64)
+    out = np.zeros(cap, np.uint64)
+    nin, nout, unsorted, disorder = (ctypes.c_uint32() for _ in range(4))
+    status = np.zeros(3, np.uint32)
+    vp = ctypes.c_void_p
+    lib.sim_pq(ctypes.c_uint32(nwaves), ctypes.c_uint32(pnum), ctypes.c_uint32(nb_log2), ctypes.c_uint32(rounds),
+               ctypes.c_uint32(pop_every), ctypes.c_uint32(dmax), ctypes.c_uint64(seed), vp(ins.ctypes.data),
+               ctypes.byref(nin), vp(out.ctypes.data), ctypes.byref(nout), ctypes.byref(unsorted),
+               ctypes.byref(disorder), vp(status.ctypes.data))
+    return ins[:nin.value], out[:nout.value], unsorted.value, disorder.value, status
+
+
+@pytest.mark.parametrize("dmax", [1000, 7])
+def test_priority_queue_single_wave_is_exact(sim, dmax):
+    """One wave writes 24 batches of 1..64 elements, then takes everything:
+    the batched heap returns every element once, each taken batch ascending,
+    and the whole sequence in ascending distance order (an exact priority
+    queue; dmax = 7 makes most keys tie on distance)."""
+    ins, out, unsorted, disorder, st = _sim_pq(sim, 1, 1, 5, 24, 0, dmax, 11)
+    assert st[0] == 0 and st[2] == 0
+    assert st[1] == ins.size
+    assert np.array_equal(np.sort(ins), np.sort(out))
+    assert unsorted == 0 and disorder == 0
+
+
+@pytest.mark.parametrize("nwaves,pnum,pop_every", [(6, 1, 2), (6, 1, 1), (8, 3, 2), (5, 4, 3)])
+def test_priority_queues_concurrent_conserve_elements(sim, nwaves, pnum, pop_every):
+    """Several waves write and take concurrently (per-node locks, hand-over-hand
+    insertion, sinking deletions; pnum > 1 is the multi-queue): no element is
+    lost or duplicated, every taken batch is ascending, the queues end empty
+    and the termination count (pq_in) equals the elements written."""
+    ins, out, unsorted, _, st = _sim_pq(sim, nwaves, pnum, 7, 30, pop_every, 100000, 5 + nwaves)
+    assert st[0] == 0, f"device status {st[0]}"
+    assert st[1] == ins.size and st[2] == 0
+    assert np.array_equal(np.sort(ins), np.sort(out))
+    assert unsorted == 0
+
+
+def test_priority_queue_capacity_is_reported(sim):
+    """More full batches than the heap has nodes: the write reports the
+    capacity status (the library then retries with a larger heap)."""
+    _, _, _, _, st = _sim_pq(sim, 1, 1, 3, 24, 0, 1000, 3)
+    assert st[0] == 1
