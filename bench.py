@@ -313,10 +313,12 @@ def _percentiles(lat):
     return float(np.percentile(a, 50)), float(np.percentile(a, 99))
 
 
-def bench_serve(mlmq, torch, nreq, load, budget_gb, seed=7):
+def bench_serve(mlmq, torch, nreq, load, budget_gb, seed=7, rate=None, legs=("fifo", "server")):
     """Poisson arrivals over five resident graphs, served by the
     continuous-batching server and, on the same trace, by a FIFO loop of plain
-    solves. Latency = completion - arrival."""
+    solves. Latency = completion - arrival. rate (q/s) fixes the arrival rate
+    (else load x the FIFO service rate measured on the head of the trace);
+    legs picks which of the two runs (a long trace may be split over runs)."""
     csrs = [gg.grid(512, 512, 0.05, seed=11), gg.grid(2048, 2048, 0.05, seed=12), gg.rmat(20, 16, seed=13),
             gg.rmat(22, 16, seed=14), gg.uniform(1 << 22, 1 << 25, wmax=65535, seed=15)]
     names = ["grid512", "grid2048", "rmat20", "rmat22", "uniform4M"]
@@ -336,14 +338,17 @@ def bench_serve(mlmq, torch, nreq, load, budget_gb, seed=7):
         mlmq.sssp(graphs[gid[i]], int(src[i]), out=per_graph[gid[i]], stream=stream)
     torch.cuda.synchronize()
     mu = probe / (time.perf_counter() - t0)
-    lam = load * mu
+    lam = rate if rate else load * mu
     arrive = np.cumsum(rng.exponential(1.0 / lam, nreq))
-    log(f"[bench] serve: FIFO service rate {mu:.1f} q/s, arrivals at {lam:.1f} q/s ({load}x)")
+    log(f"[bench] serve: FIFO service rate {mu:.1f} q/s, arrivals at {lam:.1f} q/s "
+        f"({'fixed' if rate else str(load) + 'x'})")
 
     # FIFO loop of plain solves
     fifo_lat, t_start = [], time.perf_counter()
     keep = {}
-    for i in range(nreq):
+    for i in range(nreq if "fifo" in legs else 0):
+        if i % 500 == 0:
+            log(f"[bench] serve: FIFO loop at request {i}")
         now = time.perf_counter() - t_start
         if now < arrive[i]:
             time.sleep(arrive[i] - now)
@@ -355,8 +360,15 @@ def bench_serve(mlmq, torch, nreq, load, budget_gb, seed=7):
             keep[i] = mlmq.to_numpy(per_graph[g]).copy()
     fifo_span = time.perf_counter() - t_start - arrive[0]
     log(f"[bench] serve: FIFO loop done in {fifo_span:.1f}s")
+    if "server" not in legs:
+        f50, f99 = _percentiles(fifo_lat)
+        for g in graphs:
+            g.close()
+        return dict(requests=nreq, graphs=names, arrival_rate_qps=lam, fifo_service_rate_qps=mu, load=load,
+                    fifo_qps=nreq / fifo_span if fifo_lat else None, fifo_p50_ms=f50 * 1e3, fifo_p99_ms=f99 * 1e3, legs=list(legs))
 
-    # continuous-batching server
+    # continuous-batching server (one output buffer per graph and slot in
+    # flight would do; a buffer per request keeps every result for the checks)
     outs = [mlmq.new_dist(csrs[g].n) for g in gid]
     torch.cuda.synchronize()
     srv = mlmq.Server(graphs, mem_budget_bytes=int(budget_gb * (1 << 30)), max_slots=64)
@@ -364,6 +376,8 @@ def bench_serve(mlmq, torch, nreq, load, budget_gb, seed=7):
     t_start = time.perf_counter()
     try:
         for i in range(nreq):
+            if i % 500 == 0:
+                log(f"[bench] serve: server at request {i}")
             now = time.perf_counter() - t_start
             if now < arrive[i]:
                 time.sleep(arrive[i] - now)
@@ -375,22 +389,23 @@ def bench_serve(mlmq, torch, nreq, load, budget_gb, seed=7):
     t0_ns = times[0][0] - int(arrive[0] * 1e9)
     srv_lat = [(b - t0_ns) / 1e9 - arrive[i] for i, (a, b) in enumerate(times)]
     srv_span = (max(b for _, b in times) - t0_ns) / 1e9 - arrive[0]
-    same = all(np.array_equal(mlmq.to_numpy(outs[i]), keep[i]) for i in keep)
+    same = all(np.array_equal(mlmq.to_numpy(outs[i]), keep[i]) for i in keep) if keep else None
     # CPU baseline: the oracle on the trace's requests in arrival order, one per
     # thread, for about 20 s; each vector is compared with the served one
     cpu, cpu_equal = oracle_pool([csrs[g] for g in gid], [int(x) for x in src], lambda i: mlmq.to_numpy(outs[i]),
                                  f"the {nreq} requests in arrival order", max_seconds=20.0)
-    f50, f99 = _percentiles(fifo_lat)
+    f50, f99 = _percentiles(fifo_lat) if fifo_lat else (float("nan"), float("nan"))
     s50, s99 = _percentiles(srv_lat)
     res = dict(requests=nreq, graphs=names, arrival_rate_qps=lam, fifo_service_rate_qps=mu, load=load,
                mem_budget_gb=budget_gb,
                server_qps=nreq / srv_span, server_p50_ms=s50 * 1e3, server_p99_ms=s99 * 1e3,
-               fifo_qps=nreq / fifo_span, fifo_p50_ms=f50 * 1e3, fifo_p99_ms=f99 * 1e3,
+               fifo_qps=nreq / fifo_span if fifo_lat else None, fifo_p50_ms=f50 * 1e3, fifo_p99_ms=f99 * 1e3,
                statuses_ok=all(x == 0 for x in status), served_equals_alone=same, compared=len(keep),
                cpu_baseline=cpu, oracle_equal=cpu_equal)
     log(f"[bench] serve: server {res['server_qps']:.1f} q/s p50 {res['server_p50_ms']:.2f} ms "
-        f"p99 {res['server_p99_ms']:.2f} ms | FIFO {res['fifo_qps']:.1f} q/s p50 {res['fifo_p50_ms']:.2f} ms "
-        f"p99 {res['fifo_p99_ms']:.2f} ms | same={same}")
+        f"p99 {res['server_p99_ms']:.2f} ms | FIFO {res['fifo_qps'] or float('nan'):.1f} q/s "
+        f"p50 {res['fifo_p50_ms']:.2f} ms p99 {res['fifo_p99_ms']:.2f} ms | same={same}")
+    res["legs"] = list(legs)
     for g in graphs:
         g.close()
     return res
@@ -533,6 +548,8 @@ def main():
     ap.add_argument("--serve", type=int, default=2000, help="serving requests (0 = skip)")
     ap.add_argument("--serve-load", type=float, default=1.5, help="arrival rate / FIFO service rate")
     ap.add_argument("--serve-budget-gb", type=float, default=8.0)
+    ap.add_argument("--serve-rate", type=float, default=0.0, help="fixed arrival rate in q/s (0 = load x FIFO rate)")
+    ap.add_argument("--serve-legs", default="fifo,server", help="which serving runs: fifo, server or both")
     ap.add_argument("--bare", action="store_true",
                     help="only the warm-up and timed solves of each workload (for counter passes)")
     ap.add_argument("--summarize-counters", default="",
@@ -634,7 +651,8 @@ def main():
     for s in results.values():
         s["achieved_vs_stream"] = s["achieved_gbs"] / stream_gbs
     batch = bench_batch(mlmq, torch, args.tune_ms) if args.batch else None
-    serving = bench_serve(mlmq, torch, args.serve, args.serve_load, args.serve_budget_gb) if args.serve else None
+    serving = bench_serve(mlmq, torch, args.serve, args.serve_load, args.serve_budget_gb, rate=args.serve_rate or None,
+                          legs=tuple(args.serve_legs.split(","))) if args.serve else None
     pq = pq_study(mlmq, torch) if args.pq_study else None
 
     p = primary

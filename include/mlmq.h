@@ -270,7 +270,6 @@ int mlmq_latency_probe(const mlmq_graph* g, uint32_t source, uint32_t hops, void
                        double* handoff_ns_out);
 
 /*
- * Many queries in one persistent launch./*
  * Many queries in one persistent launch. Query i solves graphs[i] from
  * sources[i] into dist_outs[i] (device memory, n_i uint32 each). cfgs may be
  * NULL (per-graph autotuned/default) or hold one config per query; launch
