@@ -170,8 +170,9 @@ int mlmq_graph_info(const mlmq_graph* g, int32_t* n, int64_t* m, mlmq_features* 
 
 /*
  * The config a solve on g uses when cfg == NULL: the autotuned one if
- * mlmq_autotune ran, else defaults adjusted by the Table 2 features.
- * out->struct_size must be set; stream and stats_out are left NULL.
+ * mlmq_autotune ran, else the learned selector's top template for g's Table 2
+ * features (mlmq_select), else (no model built in) defaults adjusted by the
+ * features. out->struct_size must be set; stream and stats_out are left NULL.
  */
 int mlmq_graph_config(const mlmq_graph* g, mlmq_config* out);
 
@@ -184,8 +185,8 @@ int mlmq_features_host(int32_t n, int64_t m, const int32_t* row_offsets, const i
 
 /*
  * Single-source solve (Section 2.1 / Section 4.1). dist_out: n uint32, host or
- * device memory, caller-owned; receives L(s). cfg NULL = the autotuned config
- * cached for this graph if any, else defaults. Enqueues on cfg->stream and
+ * device memory, caller-owned; receives L(s). cfg NULL = the graph's config
+ * (mlmq_graph_config: autotuned, else the selector's pick). Enqueues on cfg->stream and
  * returns after the solve finished. source >= n gives MLMQ_ERR_INVALID_ARG.
  * MLMQ_ERR_DISTANCE_OVERFLOW if a reachable vertex's distance is >= 2^32 - 1.
  * MLMQ_ERR_TIMEOUT if the device watchdog fired.
@@ -297,8 +298,8 @@ int mlmq_sssp_batch(const mlmq_graph* const* graphs, const uint32_t* sources, ui
 int32_t mlmq_candidate_count(void);
 
 /*
- * Template t as a config for graph g (t = -1: the feature-driven default that
- * cfg == NULL uses before any tuning). out->struct_size must be set; its
+ * Template t as a config for graph g (t = -1: the feature-driven default,
+ * which cfg == NULL falls back to without a model). out->struct_size must be set; its
  * stream and stats_out are kept. Needs a device (the launch size depends on
  * its compute units). MLMQ_ERR_INVALID_ARG for t out of range.
  */
@@ -321,9 +322,10 @@ int mlmq_select_inputs(const mlmq_features* f, int32_t t, float* x);
 int mlmq_select_rank(const mlmq_features* f, int32_t* order, float* scores, int32_t cap);
 
 /*
- * The selector's top template for g as a config, without timing anything and
- * without caching it (the feature-driven default if no model is built in).
- * out->struct_size must be set; stream and stats_out are kept.
+ * The selector's top template for g as a config, without timing anything
+ * (the feature-driven default if no model is built in); it is what cfg ==
+ * NULL uses until mlmq_autotune caches a timed choice. out->struct_size must
+ * be set; stream and stats_out are kept.
  */
 int mlmq_select(const mlmq_graph* g, mlmq_config* out);
 

@@ -268,6 +268,7 @@ extern "C" int mlmq_graph_create(int32_t n, int64_t m, const int32_t* row_offset
   g->max_w = maxw;
   g->min_w = m ? minw : 1u;
   g->overflow_safe = (uint64_t)(n - 1) * (uint64_t)maxw < (uint64_t)kInf;
+  g->sel_template = selector_pick(g->features);
   std::vector<uint64_t> adj((size_t)m);
   for (int64_t e = 0; e < m; ++e) adj[e] = (uint32_t)hcol[e] | ((uint64_t)hw[e] << 32);
   hipError_t e = hipMalloc(&g->d_off, sizeof(int32_t) * ((size_t)n + 1));
@@ -694,7 +695,7 @@ const mlmq_config* resolve_config(const mlmq_graph* g, const mlmq_config* cfg, m
   std::lock_guard<std::mutex> lk(const_cast<mlmq_graph*>(g)->mu);
   if (g->has_tuned) {
     *tmp = g->tuned;
-  } else {
+  } else if (g->sel_template < 0 || template_config(g, g->sel_template, tmp) != MLMQ_OK) {
     tmp->struct_size = sizeof(mlmq_config);
     default_config(tmp);
     heuristic_config(g, tmp);

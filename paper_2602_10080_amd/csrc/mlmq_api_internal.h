@@ -26,6 +26,7 @@ struct mlmq_graph {
   std::mutex mu;
   bool has_tuned = false;
   mlmq_config tuned{};
+  int32_t sel_template = -1;  // the selector's top template (-1: the feature heuristic)
 };
 
 namespace mlmq {
@@ -72,6 +73,10 @@ int need_device();
 int check_config(const mlmq_config* c);
 void default_config(mlmq_config* c);
 void heuristic_config(const mlmq_graph* g, mlmq_config* c);
+// Candidate template t (-1: the feature heuristic) as a config for g.
+int template_config(const mlmq_graph* g, int32_t t, mlmq_config* out);
+// The selector's top template for a graph with features f (-1 without a trained model).
+int32_t selector_pick(const mlmq_features& f);
 const mlmq_config* resolve_config(const mlmq_graph* g, const mlmq_config* cfg, mlmq_config* tmp);
 uint64_t count_degree_above(const mlmq_graph* g, uint32_t th);
 QueryPlan plan_query(const mlmq_graph* g, const mlmq_config& c, uint32_t extra_nb_log2, uint32_t hub_scale);

@@ -174,8 +174,14 @@ uint32_t pow2_log_nearest(double x) {
   return (uint32_t)std::min(31.0, std::max(0.0, std::floor(l + 0.5)));
 }
 
+}  // namespace
+
+namespace mlmq {
+
+int32_t selector_pick(const mlmq_features& f) { return kSelTrees ? ranked(f, nullptr)[0] : -1; }
+
 // Template t (or the feature-driven default for t = -1) as a config for g.
-int materialise(const mlmq_graph* g, int32_t t, mlmq_config* out) {
+int template_config(const mlmq_graph* g, int32_t t, mlmq_config* out) {
   mlmq_config c;
   c.struct_size = sizeof(mlmq_config);
   default_config(&c);
@@ -203,6 +209,10 @@ int materialise(const mlmq_graph* g, int32_t t, mlmq_config* out) {
   *out = c;
   return MLMQ_OK;
 }
+
+}  // namespace mlmq
+
+namespace {
 
 void keep_caller_fields(mlmq_config* out, const mlmq_config& c) {
   mlmq_stats* so = out->stats_out;
@@ -241,7 +251,7 @@ extern "C" int mlmq_candidate_config(const mlmq_graph* g, int32_t t, mlmq_config
   int rc = need_device();
   if (rc) return rc;
   mlmq_config c;
-  rc = materialise(g, t, &c);
+  rc = template_config(g, t, &c);
   if (rc) return rc;
   keep_caller_fields(out, c);
   return MLMQ_OK;
@@ -253,9 +263,9 @@ extern "C" int mlmq_select(const mlmq_graph* g, mlmq_config* out) {
     return set_error(MLMQ_ERR_INVALID_ARG, "config struct_size %u != %zu", out->struct_size, sizeof(mlmq_config));
   int rc = need_device();
   if (rc) return rc;
-  const int32_t t = kSelTrees ? ranked(g->features, nullptr)[0] : -1;
+  const int32_t t = selector_pick(g->features);
   mlmq_config c;
-  rc = materialise(g, t, &c);
+  rc = template_config(g, t, &c);
   if (rc) return rc;
   keep_caller_fields(out, c);
   return MLMQ_OK;
@@ -303,7 +313,7 @@ extern "C" int mlmq_autotune(mlmq_graph* g, uint32_t budget_ms, mlmq_config* out
   const auto t0 = std::chrono::steady_clock::now();
   double best_ms = 1e300;
   mlmq_config best;
-  rc = materialise(g, -1, &best);
+  rc = template_config(g, -1, &best);
   if (rc) {
     (void)hipFree(d_dist);
     return rc;
@@ -312,7 +322,7 @@ extern "C" int mlmq_autotune(mlmq_graph* g, uint32_t budget_ms, mlmq_config* out
     const double el = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     if (ci > 0 && el > budget_ms) break;
     mlmq_config c;
-    if (materialise(g, cand[ci], &c) != MLMQ_OK) continue;
+    if (template_config(g, cand[ci], &c) != MLMQ_OK) continue;
     const mlmq_config keep = c;
     mlmq_stats st;
     std::memset(&st, 0, sizeof(st));

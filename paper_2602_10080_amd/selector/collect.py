@@ -66,6 +66,18 @@ def corpus():
                 out.append((f"uniform{lg}-d{deg}-w{wmax}",
                             (lambda lg=lg, deg=deg, wmax=wmax, s=seed:
                              gg.uniform(1 << lg, deg << lg, wmax=wmax, seed=s))))
+    # the largest sizes the library is benchmarked at (other seeds than the
+    # benchmark graphs): launch size and L1 capacity move with the graph size
+    seed += 1
+    out.append(("uniform22-d8-w65535", (lambda s=seed: gg.uniform(1 << 22, 8 << 22, wmax=65535, seed=s))))
+    seed += 1
+    out.append(("rmat23-ef16-a0.57-w255", (lambda s=seed: gg.rmat(23, 16, seed=s))))
+    seed += 1
+    out.append(("grid3072x3072-p0.05-w255", (lambda s=seed: gg.grid(3072, 3072, 0.05, seed=s))))
+    seed += 1
+    out.append(("rmat23-ef8-a0.57-w255", (lambda s=seed: gg.rmat(23, 8, seed=s))))
+    seed += 1
+    out.append(("rmat22-ef16-a0.45-w255", (lambda s=seed: gg.rmat(22, 16, 0.45, 0.22, 0.22, seed=s))))
     return out
 
 
@@ -77,6 +89,7 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("out")
     ap.add_argument("--only", default="", help="comma-separated graph indices (default: all)")
+    ap.add_argument("--append", action="store_true", help="append rows to OUT (no header)")
     ap.add_argument("--reps", type=int, default=1, help="timed runs per (source, template); the minimum is kept")
     args = ap.parse_args()
 
@@ -92,9 +105,10 @@ def main():
               "edges", "expansions", "equal"]
     t_all = time.perf_counter()
     mismatches = 0
-    with open(args.out, "w", newline="") as fh:
+    with open(args.out, "a" if args.append else "w", newline="") as fh:
         wr = csv.writer(fh)
-        wr.writerow(fields)
+        if not args.append:
+            wr.writerow(fields)
         for gi in pick:
             name, make = graphs[gi]
             t0 = time.perf_counter()
