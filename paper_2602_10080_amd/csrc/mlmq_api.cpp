@@ -334,6 +334,12 @@ QueryPlan plan_query(const mlmq_graph* g, const mlmq_config& c, uint32_t extra_n
   }
   // rings: 2^nb_log2 blocks; heaps: node 0 (partial buffer) + 2^nb_log2 - 1 tree nodes
   p.nb_log2 = log2_ceil((cap + 63) / 64 + (pq ? 1 : 0)) + extra_nb_log2;
+  // Bucket rings fill with partly filled blocks (the head bucket and those past
+  // the write-combining window are written at once, a few elements a block),
+  // so on large graphs they get four times the blocks their element count
+  // needs (RMAT-23 with a near-far or filter L1 over buckets otherwise takes
+  // two capacity retries).
+  if (c.l2_type == MLMQ_L2_BUCKET && !c.l2_capacity && g->n >= (1 << 20)) p.nb_log2 += 2;
   p.nb_log2 = std::max<uint32_t>(p.nb_log2, 4);
   uint64_t hubs = c.th_hub ? count_degree_above(g, c.th_hub) : 0;
   p.hub_cap = c.th_hub ? (uint32_t)std::min<uint64_t>(std::max<uint64_t>(1024, 4 * hubs) * hub_scale, 1u << 26) : 1;
