@@ -492,6 +492,14 @@ COUNTER_PASSES = {
              "TCC_EA0_ATOMIC_sum"],
     "cache": ["TCC_HIT_sum", "TCC_MISS_sum", "SQ_INSTS_LDS", "SQ_LDS_BANK_CONFLICT", "SQ_WAVE_CYCLES",
               "SQ_BUSY_CYCLES", "SQ_WAIT_INST_ANY"],
+    # instruction issue: how much of a wave's life is spent issuing, and what
+    "issue": ["SQ_WAVES", "SQ_WAVE_CYCLES", "SQ_WAIT_ANY", "SQ_ACTIVE_INST_ANY", "SQ_INSTS_VALU", "SQ_INSTS_SALU",
+              "SQ_INSTS_VMEM", "SQ_INSTS_SMEM"],
+    "issue2": ["SQ_ACTIVE_INST_VALU", "SQ_ACTIVE_INST_SCA", "SQ_ACTIVE_INST_LDS", "SQ_ACTIVE_INST_VMEM",
+               "SQ_INSTS_BRANCH", "SQ_INSTS_LDS", "SQ_WAIT_INST_LDS", "SQ_WAVE_CYCLES"],
+    # instruction and scalar data caches
+    "icache": ["SQC_ICACHE_REQ", "SQC_ICACHE_HITS", "SQC_ICACHE_MISSES", "SQC_ICACHE_MISSES_DUPLICATE",
+               "SQC_DCACHE_REQ", "SQC_DCACHE_HITS", "SQC_DCACHE_MISSES", "SQC_TC_INST_REQ"],
 }
 
 

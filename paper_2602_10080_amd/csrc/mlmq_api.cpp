@@ -337,9 +337,10 @@ QueryPlan plan_query(const mlmq_graph* g, const mlmq_config& c, uint32_t extra_n
   // Bucket rings fill with partly filled blocks (the head bucket and those past
   // the write-combining window are written at once, a few elements a block),
   // so on large graphs they get four times the blocks their element count
-  // needs (RMAT-23 with a near-far or filter L1 over buckets otherwise takes
-  // two capacity retries).
-  if (c.l2_type == MLMQ_L2_BUCKET && !c.l2_capacity && g->n >= (1 << 20)) p.nb_log2 += 2;
+  // needs, eight times from 4M vertices (a power-law graph of 8M vertices
+  // with a near-far or filter L1 over 64-wide buckets peaks at two to four
+  // times; the 8M-vertex plan takes 32 rings x 2^18 blocks, 4.3 GB).
+  if (c.l2_type == MLMQ_L2_BUCKET && !c.l2_capacity && g->n >= (1 << 20)) p.nb_log2 += g->n >= (1 << 22) ? 3 : 2;
   p.nb_log2 = std::max<uint32_t>(p.nb_log2, 4);
   uint64_t hubs = c.th_hub ? count_degree_above(g, c.th_hub) : 0;
   p.hub_cap = c.th_hub ? (uint32_t)std::min<uint64_t>(std::max<uint64_t>(1024, 4 * hubs) * hub_scale, 1u << 26) : 1;

@@ -135,7 +135,8 @@ struct Ctx {
   uint32_t thresh;           // NF (near-far) or F (filter)
   uint32_t wcount;           // L1 writes since the last periodic flush
   uint32_t done_acc;         // blocks / hub chunks taken, not yet added to done
-  uint32_t pend;             // lane r: claimed but unpublished ticket of ring r
+  uint32_t pend;             // lane r: claimed but unpublished ticket of ring r; with one ring,
+                             // lane 1: claims still allowed without reading its counters (kInf = none)
   const uint32_t* cancel;    // host-set flag: stop now
   uint64_t deadline;         // device watchdog (wall-clock ticks)
   uint64_t cap_wait;         // longest wait for a free L2 slot
@@ -776,9 +777,21 @@ __device__ __forceinline__ bool l2_read(Ctx& c, uint64_t& e, bool& ok) {
   if (c.q.nrings == 1) {
     uint32_t t = 0, h = 0;
     if (lane_val(c.pend, 0) == kInf) {
-      t = uni(ld32(&c.q.rings[0].tail.v));
-      h = uni(ld32(&c.q.rings[0].head.v));
-      if ((int32_t)(t - h) <= 0) return false;
+      const uint32_t credit = lane_val(c.pend, 1);
+      if (credit != kInf && credit != 0u) {
+        // the ring held many blocks when last read: claim by atomicAdd at
+        // once, one memory round trip fewer (an overshoot is a pending claim
+        // that a later write fills, as on the atomicAdd path below)
+        if (lane() == 1) c.pend = credit - 1u;
+        t = 65u;
+        h = 0u;
+      } else {
+        t = uni(ld32(&c.q.rings[0].tail.v));
+        h = uni(ld32(&c.q.rings[0].head.v));
+        if ((int32_t)(t - h) <= 0) return false;
+        // a few claims without looking, if the backlog dwarfs them
+        if (lane() == 1) c.pend = (int32_t)(t - h) > 1024 ? 3u : kInf;
+      }
     }
     return l2_try_ring(c, 0, t, h, e, ok);
   }
