@@ -99,11 +99,13 @@ def test_kernel_on_cpu_matches_oracle(sim, graph, cfg):
 
 
 @pytest.mark.parametrize("cfg", ["L0x2-L1V-L2V", "L1FQ-L2DQ-hub", "L0x1-L1NF-L2PQ"])
-@pytest.mark.parametrize("nslots,want", [(2, 3), (3, 8)])
-def test_server_kernel_on_cpu_matches_oracle(sim, cfg, nslots, want):
-    """Slot protocol of the resident server kernel: queries join, run next to
-    each other, close, and the last wave out reports completion; each result
-    equals the oracle's. 6 waves, so queries share the grid when want < 6."""
+@pytest.mark.parametrize("nslots,want,nwg", [(2, 3, 6), (3, 8, 6), (1, 5, 16)])
+def test_server_kernel_on_cpu_matches_oracle(sim, cfg, nslots, want, nwg):
+    """Slot protocol of the resident server kernel: queries join (one ticket
+    each; waves that lose the race to a full slot count past want and stay
+    out), run next to each other, close, and the last wave out reports
+    completion; each result equals the oracle's. Queries share the grid when
+    want < nwg; with one slot and 16 waves for 5 places most joins lose."""
     csr, _ = GRAPHS["road24"]()
     srcs = np.array([0, 77, 479, 200, 13, 77, 301], np.uint32)
     nq = len(srcs)
@@ -117,7 +119,7 @@ def test_server_kernel_on_cpu_matches_oracle(sim, cfg, nslots, want):
     sim.sim_server.restype = ctypes.c_int
     rc = sim.sim_server(ctypes.c_int32(csr.n), vp(off.ctypes.data), vp(col.ctypes.data), vp(w.ctypes.data),
                         ctypes.c_int32(nq), vp(srcs.ctypes.data), vp(dist.ctypes.data), vp(k.ctypes.data),
-                        ctypes.c_uint32(6), ctypes.c_int32(nslots), ctypes.c_uint32(want),
+                        ctypes.c_uint32(nwg), ctypes.c_int32(nslots), ctypes.c_uint32(want),
                         vp(status.ctypes.data))
     assert rc == 0, "not every query completed"
     assert (status == 0).all(), status
