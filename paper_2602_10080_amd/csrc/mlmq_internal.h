@@ -59,7 +59,8 @@ struct QueryCtrl {
   Word hub_head;   // first hub record that may still have chunks
   Word hub_units;  // hub chunks reserved (termination count)
   Word joined;     // workgroups that joined this query
-  Word finished;   // workgroups that left this query
+  Word finished;   // workgroups that left this query (server queries: low 16 bits; the high
+                   // 16 bits hold the number of waves on the query, set by the first to leave)
   Word hungry;     // waves of this query that currently find no work
   Word active;     // waves currently working on this query
   Word pq_in;      // elements written to the L2 priority queues (termination count)
