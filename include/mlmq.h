@@ -58,6 +58,21 @@ extern "C" {
  */
 #define MLMQ_MEM_HOST 0u   /* CSR arrays are host memory; they are copied to the device */
 #define MLMQ_MEM_DEVICE 1u /* CSR arrays are device memory; they are copied on the device */
+/*
+ * Large power-law graphs (at least 2^22 vertices, largest degree at least 16
+ * times the mean) also get a second device copy whose vertex ids are
+ * renumbered by decreasing degree, so that the labels of the high-degree
+ * vertices, which most edges point to, share cache lines (on smaller graphs,
+ * whose labels stay in cache anyway, it measured slower). Plain solves
+ * (mlmq_sssp, mlmq_bfs, mlmq_autotune) run on that copy and gather the result
+ * back into the caller's vertex order before they return; batches, servers,
+ * mlmq_check, mlmq_latency_probe and mlmq_sssp_noalloc use the graph as given.
+ * The copy costs the graph's memory once more plus 4 bytes per vertex.
+ * MLMQ_GRAPH_KEEP_ORDER leaves it out; MLMQ_GRAPH_DEGREE_ORDER makes it for
+ * any graph with edges. Setting both is an error.
+ */
+#define MLMQ_GRAPH_KEEP_ORDER 2u
+#define MLMQ_GRAPH_DEGREE_ORDER 4u
 
 /* L1 (per-workgroup LDS) queue types, Section 3.4 and Table 1 */
 #define MLMQ_L1_NONE 0    /* no L1: L0 spills straight to L2 */
@@ -160,7 +175,8 @@ int mlmq_config_default(mlmq_config* cfg);
  * row_offsets[n+1] (row_offsets[0] = 0, non-decreasing, row_offsets[n] = m),
  * col[m] in [0, n), w[m] any uint32 (0, self-loops and parallel edges allowed).
  * flags: MLMQ_MEM_HOST or MLMQ_MEM_DEVICE tells where the arrays live; they
- * are copied, so the caller keeps ownership. Validation is O(n+m); errors give
+ * are copied, so the caller keeps ownership; MLMQ_GRAPH_KEEP_ORDER or
+ * MLMQ_GRAPH_DEGREE_ORDER may be or-ed in (the degree-ordered copy, see above). Validation is O(n+m); errors give
  * MLMQ_ERR_INVALID_ARG. Needs a HIP device (else MLMQ_ERR_DEVICE).
  */
 int mlmq_graph_create(int32_t n, int64_t m, const int32_t* row_offsets, const int32_t* col,

@@ -32,6 +32,7 @@ L1_NONE, L1_VEC, L1_NEARFAR, L1_FILTER, L1_SLF = 0, 1, 2, 3, 4
 RELAX_PRECHECK, RELAX_ATOMIC = 0, 1
 L2_FIFO, L2_BUCKET, L2_PQ = 0, 1, 2
 MEM_HOST, MEM_DEVICE = 0, 1
+GRAPH_KEEP_ORDER, GRAPH_DEGREE_ORDER = 2, 4
 
 # C-ABI entry points declared in include/mlmq.h
 EXPORTS = (
@@ -197,7 +198,7 @@ class Graph:
     """A device-resident graph. Build from any object with n, off, col, w
     (e.g. graphgen.Csr) or from arrays; torch CUDA tensors are read on device."""
 
-    def __init__(self, n: int, off, col, w):
+    def __init__(self, n: int, off, col, w, keep_order: bool = False, degree_order: bool = False):
         self._h = ctypes.c_void_p()
         flags = MEM_HOST
         keep = []
@@ -220,14 +221,18 @@ class Graph:
             ptrs = (off.ctypes.data, col.ctypes.data, w.ctypes.data)
             m = col.size
             keep = [off, col, w]
+        if keep_order:
+            flags |= GRAPH_KEEP_ORDER
+        if degree_order:
+            flags |= GRAPH_DEGREE_ORDER
         _check(lib().mlmq_graph_create(int(n), int(m), *ptrs, flags, ctypes.byref(self._h)))
         del keep
         self.n = int(n)
         self.m = int(m)
 
     @classmethod
-    def from_csr(cls, csr) -> "Graph":
-        return cls(csr.n, csr.off, csr.col, csr.w)
+    def from_csr(cls, csr, keep_order: bool = False, degree_order: bool = False) -> "Graph":
+        return cls(csr.n, csr.off, csr.col, csr.w, keep_order=keep_order, degree_order=degree_order)
 
     @property
     def handle(self):

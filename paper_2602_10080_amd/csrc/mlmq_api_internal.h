@@ -18,6 +18,12 @@ struct mlmq_graph {
   int64_t m = 0;
   int32_t* d_off = nullptr;   // [n+1]
   uint64_t* d_adj = nullptr;  // [m] col | weight << 32
+  // degree-ordered copy (power-law graphs, for plain solves): vertex v is
+  // vertex ord_of[v] there; null when the graph keeps its order
+  int32_t* d_off_ord = nullptr;
+  uint64_t* d_adj_ord = nullptr;
+  uint32_t* d_ord_of = nullptr;     // [n] on the device
+  std::vector<uint32_t> h_ord_of;   // [n] on the host (sources)
   mlmq_features features{};
   uint64_t deg_hist[33]{};    // bucket k: degrees in [2^(k-1), 2^k), bucket 0: degree 0
   uint32_t max_w = 0;

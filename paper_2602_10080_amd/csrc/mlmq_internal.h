@@ -178,6 +178,8 @@ size_t worker_lds_bytes(uint32_t waves, uint32_t l1_cap, bool two_rings, bool st
 hipError_t launch_init(const QueryDesc* d_queries, BatchCtrl* d_batch, int nq, uint32_t max_words, hipStream_t s);
 hipError_t launch_worker(const LaunchArgs& a, uint32_t grid, uint32_t wg_size, size_t lds, hipStream_t s);
 hipError_t launch_overflow_check(const QueryDesc* d_query, uint32_t* d_flag, hipStream_t s);
+// out[v] = lab[ord_of[v]] for v < n (labels of a degree-ordered solve, back in the caller's order)
+hipError_t launch_unorder(const uint32_t* d_lab, const uint32_t* d_ord_of, uint32_t n, uint32_t* d_out, hipStream_t s);
 hipError_t launch_gather(const QueryDesc* d_queries, int nq, QueryResult* d_out, hipStream_t s);
 hipError_t worker_occupancy(uint32_t wg_size, size_t lds, bool pq, int* wgs_per_cu);
 hipError_t launch_server_worker(const ServerArgs& a, uint32_t grid, size_t lds, hipStream_t s);

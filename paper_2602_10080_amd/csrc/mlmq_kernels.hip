@@ -1682,6 +1682,14 @@ __global__ void mlmq_gather(const QueryDesc* qs, int nq, QueryResult* out) {
   for (int k = 0; k < kNumCounters; ++k) out[i].stats[k] = ctl->stats[k];
 }
 
+// Labels of a solve on the degree-ordered copy of a graph, back in the
+// caller's vertex order: out[v] = lab[ord_of[v]].
+__global__ void __launch_bounds__(256) mlmq_unorder(const uint32_t* lab, const uint32_t* ord_of, uint32_t n,
+                                                    uint32_t* out) {
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) out[v] = lab[ord_of[v]];
+}
+
 // ------------------------------------------------------------ optimality check
 
 // Edges one wave checks per slice; slices are handed out grid-stride.
@@ -1847,6 +1855,13 @@ hipError_t launch_worker(const LaunchArgs& a, uint32_t grid, uint32_t wg_size, s
 // fit into any free wave slot beside a resident server kernel.
 hipError_t launch_overflow_check(const QueryDesc* d_query, uint32_t* d_flag, hipStream_t s) {
   hipLaunchKernelGGL(mlmq_overflow_check, dim3(4096), dim3(64), 0, s, d_query, d_flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_unorder(const uint32_t* d_lab, const uint32_t* d_ord_of, uint32_t n, uint32_t* d_out, hipStream_t s) {
+  uint32_t blocks = (n + 255u) / 256u;
+  blocks = blocks < 1u ? 1u : (blocks > 16384u ? 16384u : blocks);
+  hipLaunchKernelGGL(mlmq_unorder, dim3(blocks), dim3(256), 0, s, d_lab, d_ord_of, n, d_out);
   return hipGetLastError();
 }
 

@@ -98,5 +98,10 @@ def test_device_calls_fail_cleanly_without_gpu():
     rc = mlmq.lib().mlmq_graph_create(g.n, g.m, off.ctypes.data, g.col.ctypes.data, g.w.ctypes.data, 0,
                                       ctypes.byref(h))
     assert rc == mlmq.ERR_DEVICE and not h
+    # flags are checked before the device: unknown bits, or keep-order with degree-order
+    for flags in (8, mlmq.GRAPH_KEEP_ORDER | mlmq.GRAPH_DEGREE_ORDER):
+        rc = mlmq.lib().mlmq_graph_create(g.n, g.m, off.ctypes.data, g.col.ctypes.data, g.w.ctypes.data, flags,
+                                          ctypes.byref(h))
+        assert rc == mlmq.ERR_INVALID_ARG and not h
     assert mlmq.lib().mlmq_sssp(None, 0, None, None) == mlmq.ERR_INVALID_ARG
     assert mlmq.lib().mlmq_check(None, 0, None, None, None, None) == mlmq.ERR_INVALID_ARG

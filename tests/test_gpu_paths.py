@@ -3,8 +3,9 @@ test's false alarm (a saturating candidate that is not a shortest path) in
 the plain, batched and serving forms; the device watchdog; the refusal of
 multi-wave workgroups; batches whose queue layout changes between launches;
 concurrent solves from two host threads on two streams; a server whose
-graphs are all power-law (register-bound residency); and batches and servers
-that mix priority-queue queries (their own kernel variant) with ring queries.
+graphs are all power-law (register-bound residency); batches and servers
+that mix priority-queue queries (their own kernel variant) with ring queries;
+and plain solves on a power-law graph's degree-ordered copy.
 Every result is compared with the oracle element by element (integer
 arithmetic, tolerance 0)."""
 import sys
@@ -267,3 +268,34 @@ def test_latency_probe_runs_and_leaves_graph_intact():
     with pytest.raises(mlmq.MlmqError):
         mlmq.latency_probe(g, csr.n, 16)
     g.close()
+
+
+def test_degree_ordered_copy_gathers_back():
+    """Plain solves on a graph's degree-ordered copy (made by default for large
+    power-law graphs, forced here with MLMQ_GRAPH_DEGREE_ORDER) are gathered
+    back into the caller's vertex order: shortest paths into device and host
+    buffers, and breadth-first levels, equal the oracle's, and so do those of
+    the same graph created with MLMQ_GRAPH_KEEP_ORDER (no copy). RMAT-23 at
+    full size, which gets the copy by default, is in the full-size tests."""
+    mlmq = _mlmq()
+    csr = gg.rmat(14, 16, seed=21)
+    graphs = {"ordered": mlmq.Graph.from_csr(csr, degree_order=True),
+              "kept": mlmq.Graph.from_csr(csr, keep_order=True)}
+    with pytest.raises(mlmq.MlmqError):
+        mlmq.Graph.from_csr(csr, keep_order=True, degree_order=True)
+    srcs = [gg.max_degree_vertex(csr)] + [int(x) for x in gg.sample_sources(csr, 3, seed=4)]
+    for s in srcs:
+        want, levels = oracle.dijkstra(csr, s), oracle.bfs(csr, s)
+        for name, g in graphs.items():
+            _say(f"[ordered] {name} source {s}")
+            out = mlmq.sssp(g, s)
+            torch.cuda.synchronize()
+            assert np.array_equal(mlmq.to_numpy(out), want), (name, s)
+            host = np.empty(csr.n, dtype=np.uint32)
+            mlmq.sssp(g, s, out=host)
+            assert np.array_equal(host, want), (name, s)
+            lv = mlmq.bfs(g, s)
+            torch.cuda.synchronize()
+            assert np.array_equal(mlmq.to_numpy(lv), levels), (name, s)
+    for g in graphs.values():
+        g.close()
