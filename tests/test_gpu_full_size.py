@@ -94,6 +94,25 @@ def test_rmat23_highest_degree_source():
     _solve_and_check("rmat23", csr, src, want, g=_device_graph("rmat23", csr))
 
 
+def test_rmat23_sampled_sources_host_and_device_output():
+    """RMAT-23 is solved on its degree-ordered copy (the library's default for
+    large power-law graphs) and gathered back: two more sources, into a device
+    tensor and into a host buffer, equal the oracle."""
+    mlmq = _mlmq()
+    csr, _, _ = _workload("rmat23")
+    g = _device_graph("rmat23", csr)
+    for s in gg.sample_sources(csr, 2, seed=5):
+        s = int(s)
+        want = oracle.dijkstra(csr, s)
+        _say(f"[full] rmat23 source {s}")
+        out = mlmq.sssp(g, s)
+        torch.cuda.synchronize()
+        assert np.array_equal(mlmq.to_numpy(out), want), s
+        host = np.empty(csr.n, dtype=np.uint32)
+        mlmq.sssp(g, s, out=host)
+        assert np.array_equal(host, want), s
+
+
 # The bucket L2 (Section 4.2) at full size under each L1 policy over it, and
 # SLF over buckets (the paper's best power-law combination in Section 5):
 # bucket width 2^6 around the graphs' mean weight of 128, 32 buckets.
