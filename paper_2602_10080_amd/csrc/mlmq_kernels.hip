@@ -1317,8 +1317,12 @@ __device__ __forceinline__ void run_query(Ctx& c) {
     } else if (c.q.l1_type != MLMQ_L1_NONE && !l1_empty(c)) {
       // looked at on every take while the ring is long enough to share: on
       // grids the idle waves get work a few microseconds sooner (every 16th
-      // take measured 10% slower on the 2048 x 2048 road-like grid)
-      if (c.qt - c.qh >= c.q.donate_min && uni(ld32(&c.q.ctrl->hungry.v)) != 0) donate(c);
+      // take measured 10% slower on the 2048 x 2048 road-like grid). Over a
+      // single heap only every 16th take: each donation is a block inserted
+      // at the one root lock (road-like 512 x 512 grid: 78.5 ms against 144)
+      if ((!c.pq || c.q.nrings > 1 || (c.it & 15u) == 0) && c.qt - c.qh >= c.q.donate_min &&
+          uni(ld32(&c.q.ctrl->hungry.v)) != 0)
+        donate(c);
       got = l1_take(c, e, ok);
       c.ct[kCtL1Reads] += 1;
     } else {
